@@ -1,0 +1,180 @@
+"""Throughput of the LR-spline volume renderer on one MI355X.
+
+Workload: the 1080p vector-field volume (tri-degree (2,2,2), 3 components,
+~200k elements refined along a vortex tube; |v| through the table opacity,
+hue from direction; 1920x1080 perspective view; Eq. 4 adaptive step; FP32).
+A step is one frame: one lr_render launch over the whole view with the volume
+resident in HBM.  Samples are the (ray, sample) evaluations of the schedule,
+counted by a counting launch before the timed region.
+
+Prints one JSON line: spline samples/s (value), frames/s, p50/p99 frame
+latency, the roofline object of the render kernel, and the FP64 oracle timed
+on a bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3     # MI355X published FP32 vector peak
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def flops_per_sample(p: int, ncomp: int) -> int:
+    """Algorithmic FP32 operations of one sample (transcendentals count 1):
+    position 6, local coordinates 6, Bernstein bases 3*(5 | 10), tensor
+    contraction 2*((p+1)^3+(p+1)^2+(p+1)) per component, table lookup 11,
+    compositing 13, and for 3-vectors |v| 6 and hue 7."""
+    bern = {1: 3 * 2, 2: 3 * 5, 3: 3 * 10}[p]
+    q = p + 1
+    contr = 2 * (q ** 3 + q ** 2 + q) * ncomp
+    extra = 13 if ncomp == 3 else 0
+    return 6 + 6 + bern + contr + 11 + 13 + extra
+
+
+def cpu_baseline(wl, n_rays: int, seed: int = 11):
+    """The FP64 oracle (schedule-matched mode) on n_rays seeded pixels of the
+    view, split over a fork pool of the host cores; returns samples/s."""
+    import multiprocessing as mp
+
+    from oracle import render as orr
+    from oracle.bspline import LREvaluator
+    from oracle.lookup import ElementIndex
+    view = wl.views[0]
+    rng = np.random.default_rng(seed)
+    ii = rng.integers(0, view.width, n_rays)
+    jj = rng.integers(0, view.height, n_rays)
+    ev, ei = LREvaluator(wl.spline), ElementIndex(wl.spline.elem_box)
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    chunks = np.array_split(np.arange(n_rays), cores)
+    global _CPU_JOB
+    _CPU_JOB = (wl, view, ev, ei, ii, jj)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        counts = pool.map(_cpu_chunk, chunks)
+    dt = time.perf_counter() - t0
+    return float(sum(counts)) / dt, cores, int(sum(counts)), dt
+
+
+_CPU_JOB = None
+
+
+def _cpu_chunk(idx):
+    from oracle import render as orr
+    wl, view, ev, ei, ii, jj = _CPU_JOB
+    _, ns, _ = orr.render_view(wl, view, orr.LRField(ev), eidx=ei, ii=ii[idx], jj=jj[idx])
+    return int(ns.sum())
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--blocks", type=int, default=64)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f16"])
+    ap.add_argument("--cpu-rays", type=int, default=2048, help="rays of the oracle CPU baseline (0: skip)")
+    ap.add_argument("--copy-calib", action="store_true", help="also run a plain copy of known size (counter scale)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only (--gpus 1); multi-GPU runs are not part of this build",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import lrgen
+    log("generating workload")
+    wl = lrgen.cached("config3")
+    view = wl.views[0]
+    cpu = None
+    if args.cpu_rays > 0:       # before any GPU initialisation (the pool forks)
+        log("oracle CPU baseline on %d rays" % args.cpu_rays)
+        sps, cores, nsmp, dt = cpu_baseline(wl, args.cpu_rays)
+        cpu = {"value": sps, "unit": "samples/s", "cores": cores, "kind": "oracle",
+               "sample": "%d seeded rays of the 1920x1080 view (%d samples, %.1f s), FP64, schedule-matched"
+                         % (args.cpu_rays, nsmp, dt)}
+        log("oracle %.3e samples/s on %d cores" % (sps, cores))
+
+    import torch
+
+    import paper_1707_01170_amd as P
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    vol = P.Volume(wl.spline, blocks=args.blocks, dtype=args.dtype, device=dev)
+    torch.cuda.synchronize()
+    log("volume ready in %.2f s: %d elements, forest %s" % (time.perf_counter() - t0, vol.n_elem, vol.forest.stats))
+    sc = P.Scene(vol, P.RenderParams.of(wl))
+    views = [view]
+    rgba, _, ns = P.render(sc, views, nsamples=True)
+    torch.cuda.synchronize()
+    samples = int(ns.to(torch.int64).sum().item())
+    log("samples per frame %d (%.1f per hit ray)" % (samples, samples / max(1, int((ns > 0).sum().item()))))
+    out = torch.empty_like(rgba)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(args.warmup):
+        P.render(sc, views, out=out)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        P.render(sc, views, out=out)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    times = np.array([a.elapsed_time(b) for a, b in ev])      # ms, per launch, on the launch stream
+    log("frame ms: mean %.3f p50 %.3f p99 %.3f; wall %.3f s" % (times.mean(), np.percentile(times, 50),
+                                                               np.percentile(times, 99), wall))
+    if args.copy_calib:
+        n = 256 << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 copies of %d bytes" % n)
+    fps = args.steps / wall
+    value = samples * args.steps / wall
+    fl = flops_per_sample(vol.p[0], vol.ncomp) * samples
+    kern_s = times.mean() / 1e3
+    achieved = fl / kern_s / 1e12
+    res = {
+        "metric": "spline samples/s at 1080p (frames/s, p50/p99 frame latency alongside)",
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.dtype == "f32" else "f16-storage/f32",
+        "data": "synthetic (seeded LR-spline volume; the paper's data sets are not available)",
+        "config": {"workload": "vector field (2,2,2) x3 comps, %d elements, 1920x1080 persp, adaptive step (Eq. 4)"
+                               % vol.n_elem, "samples_per_frame": samples, "forest_blocks": args.blocks},
+        "frames_per_s": fps,
+        "p50_ms": float(np.percentile(times, 50)),
+        "p99_ms": float(np.percentile(times, 99)),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "flops_per_sample": flops_per_sample(vol.p[0], vol.ncomp), "kernel_ms": times.mean()},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

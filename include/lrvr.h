@@ -1,0 +1,251 @@
+/*
+ * lrvr.h -- C ABI of the MI355X (gfx950) library for direct volume rendering
+ * of trivariate LR-spline volumes (Fuchs, Barrowclough, Hjelmervik, Dahl:
+ * "Direct interactive visualization of locally refined spline volumes for
+ * scalar and vector fields").
+ *
+ * The calls follow the paper's problem statement: an LR-spline volume (Eq. 2,
+ * Sec. 3.1) gets an element look-up structure built on the host (Sec. 3.2.1),
+ * is converted to per-element Bezier blocks (Sec. 3.2.3), and is rendered by
+ * emission-absorption ray casting (Sec. 4, Eq. 3, Alg. 2) with the adaptive
+ * sampling distance of Eq. 4.  lr_render_backward adds the adjoint of the
+ * render with respect to the Bezier coefficients and the transfer function.
+ *
+ * Conventions shared by every call
+ *  - Parameter domain [0,1]^3.  An element is a box [lo, hi) per axis, closed
+ *    at hi = 1; elements partition the domain, so every point lies in exactly
+ *    one element.  Boxes are 6 numbers: lo x, lo y, lo z, hi x, hi y, hi z.
+ *  - "device" pointers are HIP device memory owned by the caller; "host"
+ *    pointers are ordinary process memory owned by the caller.  The library
+ *    never frees caller memory and never keeps a pointer after a call returns.
+ *  - stream: a hipStream_t passed as void* (NULL = the null stream).  Device
+ *    work is enqueued asynchronously on it; the caller synchronises.
+ *  - Every call returns an lr_status.  Nothing aborts or throws.  On error
+ *    nothing has been enqueued unless the error is LR_EHIP (a launch failed),
+ *    and lr_last_error() returns a text for the calling thread.
+ *  - Only this library's kernels compute; no call falls back to the host for
+ *    device work.
+ */
+#ifndef LRVR_H
+#define LRVR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lr_status;
+#define LR_OK 0
+#define LR_EINVAL (-1)      /* bad argument: NULL pointer, size, degree, mode */
+#define LR_ENOTPOW2 (-2)    /* forest block count not a power of two in [1,512] */
+#define LR_EKNOT (-3)       /* a box coordinate is not exactly representable in FP32 */
+#define LR_ECAPACITY (-4)   /* an output buffer is too small (needed size is reported) */
+#define LR_EHIP (-5)        /* HIP runtime or launch failure */
+#define LR_EPARTITION (-6)  /* elements overlap, leave gaps or leave [0,1]^3 */
+
+#define LR_F32 0
+#define LR_F16 1
+#define LR_F64 2
+
+#define LR_STEP_FIXED 0     /* n_fixed_steps equal segments, sampled at midpoints */
+#define LR_STEP_ADAPTIVE 1  /* Eq. 4: ds = 2^-d * min side of the sample's element */
+
+#define LR_COLOR_LUT 0      /* scalar field: RGBA from the table */
+#define LR_COLOR_HUE 1      /* 3-vector field: opacity from the table at |v|,
+                               RGB = hsv(atan2(v_y, v_x)/2pi, 1, 1) */
+
+#define LR_PERSP 0
+#define LR_ORTHO 1
+
+#define LR_LEAF 0x80000000u /* head / child reference: element id in the low 31 bits */
+#define LR_MAX_VIEWS_PER_LAUNCH 16
+
+/* Text of the last non-OK status returned on the calling thread. */
+const char* lr_last_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int32_t lr_version(void);
+
+/* ------------------------------------------------------------------ k-d forest
+ * Sec. 3.2.1, Alg. 1: the domain is divided into I x J x K regular blocks;
+ * each block holds a k-d tree over the elements that intersect it (with
+ * positive volume).  A block met by one element stores that element directly.
+ * Trees are depth-balanced: at each node, for every axis the candidate split is
+ * the element face strictly inside the node region that is nearest the mean of
+ * those faces (ties: the smaller); the axis chosen minimises
+ * max(#elements with lo < s, #elements with hi > s) (ties: the larger region
+ * extent, then x < y < z).  An element straddling a split is in both subtrees.
+ *
+ * Device layout used by lr_render / lr_lookup:
+ *   heads  uint32 [bz][by][bx]: LR_LEAF | element id, or the root node index
+ *   nodes  lr_kdnode [n_nodes]
+ * Descent for a point p in block b = min(floor(p * blocks), blocks - 1):
+ *   r = heads[b]; while !(r & LR_LEAF): n = nodes[r];
+ *   r = p[n.axis] < n.split ? n.lo : n.hi;  element = r & ~LR_LEAF.
+ */
+typedef struct {
+    uint32_t lo;    /* child for p[axis] <  split: node index or LR_LEAF|element */
+    uint32_t hi;    /* child for p[axis] >= split */
+    float split;
+    uint32_t axis;  /* 0, 1, 2 */
+} lr_kdnode;
+
+typedef struct {
+    int64_t n_heads;        /* bx*by*bz */
+    int64_t n_nodes;
+    int64_t n_direct;       /* blocks whose head is an element */
+    int32_t min_depth;      /* depth of a block's tree = deepest leaf; 0 if direct */
+    int32_t max_depth;
+    double mean_depth;
+    double var_depth;       /* population variance over all blocks */
+} lr_forest_stats;
+
+typedef struct lr_forest_host lr_forest_host;   /* opaque host-side forest */
+
+/* Builds the forest on the host (the paper precomputes it on the CPU).
+ * elem_box  host double [n_elem][6]; every value in [0,1] and exact in FP32
+ *           (else LR_EKNOT); lo < hi; the boxes must tile [0,1]^3
+ *           (checked per block by volume, else LR_EPARTITION).
+ * blocks    host int32[3], each a power of two in [1, 512] (else LR_ENOTPOW2).
+ * out       receives a forest handle to free with lr_forest_free.
+ * stats     optional (NULL allowed): sizes and the depth statistics. */
+lr_status lr_build_forest(const double* elem_box, int64_t n_elem, const int32_t blocks[3],
+                          lr_forest_host** out, lr_forest_stats* stats);
+
+/* Copies a built forest into host buffers heads [n_heads] and nodes [n_nodes]
+ * (sizes from lr_forest_stats); either pointer may be NULL to skip it. */
+lr_status lr_forest_export(const lr_forest_host* f, uint32_t* heads, lr_kdnode* nodes);
+
+void lr_forest_free(lr_forest_host* f);
+
+/* Element ids of n points (device float [n][3], each coordinate in [0,1])
+ * by Alg. 1 over a forest uploaded to the device; elem_out device int32 [n]. */
+lr_status lr_lookup(const uint32_t* heads, const lr_kdnode* nodes, int64_t n_nodes,
+                    const int32_t blocks[3], int64_t n_elem, const float* points, int64_t n,
+                    int32_t* elem_out, void* stream);
+
+/* ------------------------------------------------------------- Bezier blocks
+ * Sec. 3.2.3: on each element the LR-spline is one polynomial of tri-degree p;
+ * it is rewritten in the tensor Bernstein basis of the element (a change of
+ * basis, not an approximation), giving (p1+1)(p2+1)(p3+1) coefficients per
+ * component for every element.
+ *
+ * Block layout: row e of the output holds component q's coefficient
+ * (jx, jy, jz) at q*nc + jx + (px+1)*(jy + (py+1)*jz), nc = (px+1)(py+1)(pz+1);
+ * rows are lr_bezier_stride() elements long (16-byte rows, zero padded). */
+int64_t lr_bezier_stride(const int32_t p[3], int32_t ncomp, int32_t dtype);
+
+/* Which B-splines act on which element: CSR over elements of the indices of
+ * the B-splines whose support contains the element (ascending), built on the
+ * host.  knots host double [n_bspl][3][kstride] (axis d uses p[d]+2 knots),
+ * elem_box host double [n_elem][6].  csr_ptr host int64 [n_elem+1] is always
+ * filled; csr_idx host int32 [idx_cap] is filled if idx_cap >= the count,
+ * which is returned in *nnz (else LR_ECAPACITY; pass csr_idx = NULL, idx_cap = 0
+ * to size it).  An element covered by fewer than (p1+1)(p2+1)(p3+1)
+ * B-splines is an error (LR_EPARTITION). */
+lr_status lr_build_support(const double* knots, int64_t n_bspl, int32_t kstride, const int32_t p[3],
+                           const double* elem_box, int64_t n_elem, int64_t* csr_ptr,
+                           int32_t* csr_idx, int64_t idx_cap, int64_t* nnz);
+
+typedef struct {
+    int32_t p[3];             /* tri-degree, each 1..3 */
+    int32_t ncomp;            /* components, 1..4 */
+    int32_t kstride;          /* knots per axis slot, >= max(p)+2 */
+    int32_t pad;
+    int64_t n_bspl;
+    int64_t n_elem;
+    const double* knots;      /* device [n_bspl][3][kstride] */
+    const double* coef;       /* device [n_bspl][ncomp] */
+    const double* gamma;      /* device [n_bspl] */
+    const double* elem_box;   /* device [n_elem][6] */
+    const int64_t* csr_ptr;   /* device [n_elem+1], from lr_build_support */
+    const int32_t* csr_idx;   /* device [csr_ptr[n_elem]] */
+} lr_lrspline;
+
+/* FP64 change of basis on the GPU: for every element e and B-spline i acting
+ * on it, the 1-D Bernstein coefficients of N_i's polynomial piece on e are the
+ * blossom of that piece at (lo^(p-j), hi^j) (de Boor's recurrence), and
+ *   C_e[q][j] = sum_i gamma_i c_i[q] bx_i[jx] by_i[jy] bz_i[jz]
+ * is summed in FP64 in csr order and rounded once (RNE) to out_dtype
+ * (LR_F32, LR_F16 or LR_F64).  bezier: device [n_elem][stride].
+ * range: optional device double[2]: (min, max) of all coefficients for
+ * ncomp == 1, (0, max_j |C_e[.][j]|) otherwise (FP64, before rounding). */
+lr_status lr_extract_bezier(const lr_lrspline* spl, int32_t out_dtype, void* bezier, double* range,
+                            void* stream);
+
+/* ------------------------------------------------------------------- render */
+typedef struct {
+    int32_t p[3];             /* tri-degree; the render kernels take p1 = p2 = p3 in 1..3 */
+    int32_t ncomp;            /* 1 with LR_COLOR_LUT, 3 with LR_COLOR_HUE */
+    int64_t n_elem;
+    const float* elem_box;    /* device float [n_elem][6] */
+    const void* bezier;       /* device [n_elem][stride] of bezier_dtype */
+    int32_t bezier_dtype;     /* LR_F32 or LR_F16 (FP32 arithmetic either way) */
+    int32_t blocks[3];        /* forest blocks per axis */
+    const uint32_t* heads;    /* device, from lr_forest_export */
+    const lr_kdnode* nodes;   /* device */
+    int64_t n_nodes;
+    const float* lut;         /* device float [256][4] RGBA transfer function */
+    float vmin, vmax;         /* value range mapped onto the table */
+    float xi;                 /* standard length of Alg. 2 */
+    float alpha_clamp;        /* alpha_src <- min(alpha_src, alpha_clamp) */
+    float term_alpha;         /* stop a ray once its opacity reaches this */
+    int32_t step_mode;        /* LR_STEP_FIXED or LR_STEP_ADAPTIVE */
+    int32_t n_fixed_steps;    /* for LR_STEP_FIXED, >= 1 */
+    int32_t color_mode;       /* LR_COLOR_LUT or LR_COLOR_HUE */
+    int32_t max_samples;      /* per-ray sample cap, >= 1 */
+    int32_t pad;
+} lr_scene;
+
+/* One camera (values in FP32).  Pixel (i, j), row 0 at the top, writes
+ * out[out_offset + j*width + i].  Rays (every operation an FP32 IEEE
+ * operation, no fused multiply-add, correctly rounded / and sqrt):
+ *   sx = ((2i+1)/width - 1)*tx,   sy = (1 - (2j+1)/height)*ty
+ *   LR_PERSP: d' = (fwd + sx*right) + sy*up, d = d'/sqrt((d'x^2 + d'y^2) + d'z^2), o = eye
+ *   LR_ORTHO: o = (eye + sx*right) + sy*up, d = fwd
+ * clipped to [0,1]^3 by the slab test; sample at t: clamp(o + t*d, 0, 1). */
+typedef struct {
+    int32_t proj;             /* LR_PERSP or LR_ORTHO */
+    int32_t width, height;
+    int32_t pad;
+    int64_t out_offset;       /* in pixels */
+    float eye[3], fwd[3], right[3], up[3];
+    float tx, ty;
+} lr_view;
+
+/* Forward render (Sec. 4): for every pixel of every view, march the ray
+ * (fixed steps, or Eq. 4), find each sample's element through the forest
+ * (Alg. 1), evaluate the Bezier block, map through the table and composite
+ * front to back (Alg. 2) as T_acc <- T_acc (1 - a), C += T_acc a C_src with
+ * a = 1 - (1 - alpha_src)^(ds/xi); write (C_r, C_g, C_b, 1 - T_acc).
+ * views     host array of n_views (any number; launched 16 per kernel)
+ * rgba      device float [sum of width*height][4] at the views' out_offsets
+ * nsamples  optional device uint32 [same pixels]: samples taken per pixel */
+lr_status lr_render(const lr_scene* sc, const lr_view* views, int32_t n_views, float* rgba,
+                    uint32_t* nsamples, void* stream);
+
+/* Adjoint of lr_render for scalar fields (ncomp 1, LR_COLOR_LUT, F32 blocks).
+ * Re-marches each ray with the forward's schedule (no per-sample storage) and
+ * uses the forward image to form the suffix sums.  Accumulates (+=) into
+ * grad_bezier (device float, the bezier layout) and grad_lut (device float
+ * [256][4]); the caller zeroes them.  rgba_fwd: the forward output for the
+ * same scene and views; grad_rgba: dL/d(rgba), same layout. */
+lr_status lr_render_backward(const lr_scene* sc, const lr_view* views, int32_t n_views,
+                             const float* rgba_fwd, const float* grad_rgba, float* grad_bezier,
+                             float* grad_lut, void* stream);
+
+/* Sample schedule of single rays, for verification: for pixel k
+ * (pix device int32 [n][2] = (i, j) of views[0]) writes up to max_out samples
+ * (t, element id, composited segment length) at t_out/elem_out/ds_out
+ * [k*max_out + s] (device) and the number of samples taken in count [k]. */
+lr_status lr_trace_rays(const lr_scene* sc, const lr_view* view, const int32_t* pix, int64_t n,
+                        int32_t max_out, float* t_out, int32_t* elem_out, float* ds_out,
+                        int32_t* count, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LRVR_H */

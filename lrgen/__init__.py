@@ -418,3 +418,75 @@ def small_random(p=(2, 2, 2), n=(4, 4, 4), n_ref=40, seed=0, ncomp=1, dist="unif
 
 
 CONFIGS = {1: config1, 2: config2, 3: config3, 5: config5}
+
+
+# --------------------------------------------------------------------------
+# On-disk cache of generated workloads (generation is deterministic; the
+# cache only saves time).  Keyed by the generator's sources and arguments.
+# --------------------------------------------------------------------------
+_CACHE_DIR = os.path.join(os.path.dirname(_HERE), ".lrcache")
+_MEM = {}
+
+
+def _source_key(name, kw):
+    import hashlib
+    import json
+    h = hashlib.sha1()
+    for f in (_SRC, os.path.abspath(__file__)):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    h.update(json.dumps([name, sorted(kw.items())]).encode())
+    return h.hexdigest()[:20]
+
+
+def _save(path, wl: Workload):
+    import json
+    s = wl.spline
+    views = [dict(proj=v.proj, width=v.width, height=v.height, eye=v.eye.tolist(), fwd=v.fwd.tolist(),
+                  right=v.right.tolist(), up=v.up.tolist(), tx=float(v.tx), ty=float(v.ty)) for v in wl.views]
+    meta = dict(name=wl.name, p=list(s.p), vmin=wl.vmin, vmax=wl.vmax, step_mode=wl.step_mode,
+                n_fixed_steps=wl.n_fixed_steps, color_mode=wl.color_mode, views=views, xi=wl.xi,
+                alpha_clamp=wl.alpha_clamp, term_alpha=wl.term_alpha, extra=sorted(wl.extra))
+    arrays = dict(knots=s.knots, gamma=s.gamma, coef=s.coef, elem_box=s.elem_box, lut=wl.lut,
+                  meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8))
+    for k, v in wl.extra.items():
+        arrays["extra_" + k] = np.asarray(v)
+    tmp = path + ".tmp%d.npz" % os.getpid()
+    np.savez(tmp, **arrays)
+    os.replace(tmp, path)
+
+
+def _load_file(path) -> Workload:
+    import json
+    z = np.load(path)
+    meta = json.loads(bytes(z["meta"]).decode())
+    s = LRSpline(tuple(meta["p"]), z["knots"], z["gamma"], z["coef"], z["elem_box"])
+    f = np.float32
+    views = [View(v["proj"], v["width"], v["height"], np.array(v["eye"], f), np.array(v["fwd"], f),
+                  np.array(v["right"], f), np.array(v["up"], f), f(v["tx"]), f(v["ty"])) for v in meta["views"]]
+    extra = {k: z["extra_" + k] for k in meta["extra"]}
+    return Workload(meta["name"], s, z["lut"], meta["vmin"], meta["vmax"], meta["step_mode"], meta["n_fixed_steps"],
+                    meta["color_mode"], views, meta["xi"], meta["alpha_clamp"], meta["term_alpha"], extra)
+
+
+def cached(name: str, **kw) -> Workload:
+    """getattr(lrgen, name)(**kw), memoised in memory and under .lrcache/."""
+    key = _source_key(name, kw)
+    if key in _MEM:
+        return _MEM[key]
+    path = os.path.join(_CACHE_DIR, "%s-%s.npz" % (name, key))
+    wl = None
+    if os.path.exists(path):
+        try:
+            wl = _load_file(path)
+        except Exception:
+            wl = None
+    if wl is None:
+        wl = globals()[name](**kw)
+        try:
+            os.makedirs(_CACHE_DIR, exist_ok=True)
+            _save(path, wl)
+        except OSError:
+            pass
+    _MEM[key] = wl
+    return wl

@@ -1,0 +1,52 @@
+"""Compiles the HIP library (gfx950) in-tree with hipcc."""
+from __future__ import annotations
+
+import glob
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "_lrvr.so")
+ARCH = "gfx950"
+
+HIPCC_FLAGS = [
+    "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared", "-fvisibility=hidden",
+    # packed FP32 instructions stay off (they have given wrong results on these parts)
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # sample positions rely on uncontracted, correctly rounded FP32 operations
+    "-ffp-contract=fast-honor-pragmas", "-fhip-fp32-correctly-rounded-divide-sqrt",
+    "-Wall", "-Wno-unused-result",
+]
+
+
+def _torch_lib_dir():
+    """Directory of the HIP runtime torch loads; linking against the same file
+    keeps one HIP runtime (and one set of streams) per process."""
+    try:
+        import torch
+        d = os.path.join(os.path.dirname(torch.__file__), "lib")
+        if os.path.exists(os.path.join(d, "libamdhip64.so")):
+            return d
+    except Exception:
+        pass
+    return None
+
+
+def build(verbose: bool = False) -> str:
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = ["hipcc"] + HIPCC_FLAGS + srcs + ["-o", tmp]
+    tl = _torch_lib_dir()
+    if tl:
+        cmd += ["-L" + tl, "-Wl,-rpath," + tl, "-lamdhip64"]
+    if verbose:
+        print(" ".join(cmd), file=sys.stderr)
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

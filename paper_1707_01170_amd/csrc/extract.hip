@@ -1,0 +1,245 @@
+// FP64 change of basis to Bezier blocks on the GPU (Sec. 3.2.3).
+//
+// One 64-lane wavefront per element.  Each lane takes one B-spline acting on
+// the element and computes its three 1-D Bernstein coefficient vectors on the
+// element by blossoming: the polynomial piece of a B-spline on a knot span has
+// Bernstein coefficients beta_j = blossom(lo^(p-j), hi^j), evaluated with de
+// Boor's recurrence (one knot argument per level) on the B-spline's local knot
+// vector padded by repeating its end knots.  Lanes then own output
+// coefficients and sum gamma_i c_i bx_i[jx] by_i[jy] bz_i[jz] over the
+// B-splines in csr order, so the FP64 sum is deterministic.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+
+namespace {
+
+constexpr int kLanes = 64;
+
+struct ExtractArgs {
+  int32_t p[3];
+  int32_t ncomp;
+  int32_t kstride;
+  int32_t nb;         // (p1+1)(p2+1)(p3+1)
+  int32_t dtype;
+  int32_t pad;
+  int64_t stride;     // output row length in elements of dtype
+  int64_t n_bspl;
+  int64_t n_elem;
+  const double* knots;
+  const double* coef;
+  const double* gamma;
+  const double* elem_box;
+  const int64_t* csr_ptr;
+  const int32_t* csr_idx;
+  void* out;
+  unsigned long long* range;   // order-preserving keys while the kernels run
+};
+
+// Order-preserving map of doubles to unsigned 64-bit keys (no NaNs).
+__host__ __device__ inline unsigned long long dkey(double x) {
+  unsigned long long b;
+  memcpy(&b, &x, 8);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ inline double dunkey(unsigned long long k) {
+  unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+  double x;
+  memcpy(&x, &b, 8);
+  return x;
+}
+
+// Bernstein coefficients beta[0..p] of the B-spline with local knots
+// u[0..p+1] on [a, b]; false if [a, b] is not inside one non-empty knot span.
+__device__ bool bezier_1d(const double* u, int p, double a, double b, double* beta) {
+  int s = -1;
+  for (int q = 0; q <= p; ++q)
+    if (u[q] < u[q + 1] && u[q] <= a && b <= u[q + 1]) {
+      s = q;
+      break;
+    }
+  if (s < 0) return false;
+  // Padded knot vector T[R] = u[clamp(R - p, 0, p + 1)]; the B-spline is basis
+  // function p of T and the span [u_s, u_s+1] is span k = s + p of T.
+  const int k = s + p;
+  auto T = [&](int R) {
+    int i = R - p;
+    i = i < 0 ? 0 : (i > p + 1 ? p + 1 : i);
+    return u[i];
+  };
+  for (int j = 0; j <= p; ++j) {
+    double d[4];
+    for (int r = 0; r <= p; ++r) d[r] = (k - p + r == p) ? 1.0 : 0.0;
+    for (int l = 1; l <= p; ++l) {
+      const double x = (l <= p - j) ? a : b;
+      for (int r = p; r >= l; --r) {
+        const int R = k - p + r;
+        const double tr = T(R);
+        const double al = (x - tr) / (T(R + p + 1 - l) - tr);
+        d[r] = (1.0 - al) * d[r - 1] + al * d[r];
+      }
+    }
+    beta[j] = d[p];
+  }
+  return true;
+}
+
+// FP64 -> FP16 with a single round-to-nearest-even: round to odd in FP32
+// first (keeps enough bits that the second rounding is exact), then RNE.
+__device__ inline unsigned short f64_to_f16_bits(double x) {
+  float f = (float)x;
+  const double back = (double)f;
+  if (back != x) {
+    unsigned int u = __float_as_uint(f);
+    if (fabs(back) > fabs(x)) u -= 1u;   // truncate toward zero
+    u |= 1u;                             // sticky bit
+    f = __uint_as_float(u);
+  }
+  _Float16 h = (_Float16)f;
+  unsigned short bits;
+  memcpy(&bits, &h, 2);
+  return bits;
+}
+
+__global__ void range_init(unsigned long long* r) {
+  r[0] = dkey(INFINITY);
+  r[1] = dkey(-INFINITY);
+}
+
+__global__ void range_final(unsigned long long* r) {
+  double* d = reinterpret_cast<double*>(r);
+  const double lo = dunkey(r[0]), hi = dunkey(r[1]);
+  d[0] = lo;
+  d[1] = hi;
+}
+
+__global__ __launch_bounds__(kLanes) void extract_kernel(ExtractArgs a) {
+  __shared__ double sb[kLanes][3][4];
+  __shared__ double sw[kLanes][4];
+  __shared__ double so[256];
+  const int64_t e = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int64_t b0 = a.csr_ptr[e], b1 = a.csr_ptr[e + 1];
+  const double* eb = a.elem_box + 6 * e;
+  const int NC = a.nb * a.ncomp;
+  const int px = a.p[0] + 1, py = a.p[1] + 1;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t base = b0; base < b1; base += kLanes) {
+    const int64_t q = base + lane;
+    if (q < b1) {
+      const int32_t bi = a.csr_idx[q];
+      bool ok = bi >= 0 && bi < a.n_bspl;
+      for (int d = 0; d < 3; ++d) {
+        double beta[4] = {0.0, 0.0, 0.0, 0.0};
+        if (ok) ok = bezier_1d(a.knots + ((int64_t)bi * 3 + d) * a.kstride, a.p[d], eb[d], eb[3 + d], beta);
+        for (int j = 0; j < 4; ++j) sb[lane][d][j] = beta[j];
+      }
+      for (int c = 0; c < 4; ++c)
+        sw[lane][c] = (ok && c < a.ncomp) ? a.gamma[bi] * a.coef[(int64_t)bi * a.ncomp + c] : 0.0;
+    }
+    __syncthreads();
+    const int cnt = (int)((b1 - base) < kLanes ? (b1 - base) : kLanes);
+    for (int o = 0; o < 4; ++o) {
+      const int jj = lane + kLanes * o;
+      if (jj >= NC) break;
+      const int c = jj / a.nb, j = jj % a.nb;
+      const int jx = j % px, jy = (j / px) % py, jz = j / (px * py);
+      double s = acc[o];
+      for (int m = 0; m < cnt; ++m) s += sw[m][c] * sb[m][0][jx] * sb[m][1][jy] * sb[m][2][jz];
+      acc[o] = s;
+    }
+    __syncthreads();
+  }
+  for (int o = 0; o < 4; ++o) {
+    const int jj = lane + kLanes * o;
+    if (jj < NC) so[jj] = acc[o];
+  }
+  __syncthreads();
+  for (int64_t jj = lane; jj < a.stride; jj += kLanes) {
+    const double v = jj < NC ? so[jj] : 0.0;
+    const int64_t off = e * a.stride + jj;
+    if (a.dtype == LR_F64)
+      static_cast<double*>(a.out)[off] = v;
+    else if (a.dtype == LR_F32)
+      static_cast<float*>(a.out)[off] = (float)v;
+    else
+      static_cast<unsigned short*>(a.out)[off] = f64_to_f16_bits(v);
+  }
+  if (a.range) {
+    double lo = INFINITY, hi = -INFINITY;
+    if (a.ncomp == 1) {
+      for (int jj = lane; jj < NC; jj += kLanes) {
+        lo = fmin(lo, so[jj]);
+        hi = fmax(hi, so[jj]);
+      }
+    } else {
+      lo = 0.0;
+      for (int j = lane; j < a.nb; j += kLanes) {
+        double n2 = 0.0;
+        for (int c = 0; c < a.ncomp; ++c) n2 += so[c * a.nb + j] * so[c * a.nb + j];
+        hi = fmax(hi, sqrt(n2));
+      }
+    }
+    for (int off = kLanes / 2; off > 0; off >>= 1) {
+      lo = fmin(lo, __shfl_xor(lo, off));
+      hi = fmax(hi, __shfl_xor(hi, off));
+    }
+    if (lane == 0) {
+      atomicMin(&a.range[0], dkey(lo));
+      atomicMax(&a.range[1], dkey(hi));
+    }
+  }
+}
+
+}  // namespace
+
+using lrvr::fail;
+
+LR_API lr_status lr_extract_bezier(const lr_lrspline* spl, int32_t out_dtype, void* bezier, double* range,
+                                   void* stream) {
+  if (!spl || !bezier) return fail(LR_EINVAL, "lr_extract_bezier: null pointer");
+  if (!spl->knots || !spl->coef || !spl->gamma || !spl->elem_box || !spl->csr_ptr || !spl->csr_idx)
+    return fail(LR_EINVAL, "lr_extract_bezier: null array in the spline");
+  if (spl->n_elem <= 0 || spl->n_bspl <= 0 || spl->n_elem >= (int64_t)1 << 31)
+    return fail(LR_EINVAL, "lr_extract_bezier: n_elem / n_bspl out of range");
+  if (spl->ncomp < 1 || spl->ncomp > 4) return fail(LR_EINVAL, "lr_extract_bezier: ncomp must be 1..4");
+  int pmax = 0;
+  int nb = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (spl->p[d] < 1 || spl->p[d] > 3) return fail(LR_EINVAL, "lr_extract_bezier: degree out of [1,3]");
+    pmax = spl->p[d] > pmax ? spl->p[d] : pmax;
+    nb *= spl->p[d] + 1;
+  }
+  if (spl->kstride < pmax + 2) return fail(LR_EINVAL, "lr_extract_bezier: kstride < max(p)+2");
+  if (out_dtype != LR_F32 && out_dtype != LR_F16 && out_dtype != LR_F64)
+    return fail(LR_EINVAL, "lr_extract_bezier: out_dtype must be LR_F32, LR_F16 or LR_F64");
+  if (nb * spl->ncomp > 256) return fail(LR_EINVAL, "lr_extract_bezier: more than 256 coefficients per element");
+  ExtractArgs a;
+  std::memset(&a, 0, sizeof a);
+  for (int d = 0; d < 3; ++d) a.p[d] = spl->p[d];
+  a.ncomp = spl->ncomp;
+  a.kstride = spl->kstride;
+  a.nb = nb;
+  a.dtype = out_dtype;
+  a.stride = lr_bezier_stride(spl->p, spl->ncomp, out_dtype);
+  a.n_bspl = spl->n_bspl;
+  a.n_elem = spl->n_elem;
+  a.knots = spl->knots;
+  a.coef = spl->coef;
+  a.gamma = spl->gamma;
+  a.elem_box = spl->elem_box;
+  a.csr_ptr = spl->csr_ptr;
+  a.csr_idx = spl->csr_idx;
+  a.out = bezier;
+  a.range = reinterpret_cast<unsigned long long*>(range);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (range) hipLaunchKernelGGL(range_init, dim3(1), dim3(1), 0, st, a.range);
+  hipLaunchKernelGGL(extract_kernel, dim3((unsigned)spl->n_elem), dim3(kLanes), 0, st, a);
+  if (range) hipLaunchKernelGGL(range_final, dim3(1), dim3(1), 0, st, a.range);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return fail(LR_EHIP, "lr_extract_bezier: %s", hipGetErrorString(err));
+  return LR_OK;
+}

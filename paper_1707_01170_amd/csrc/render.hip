@@ -1,0 +1,817 @@
+// Ray casting of LR-spline volumes on gfx950 (Sec. 4): forward render,
+// adjoint, single-ray traces and the forest look-up kernel.
+//
+// Mapping: one 64-lane wavefront renders an 8x8 pixel tile; a 256-thread
+// workgroup renders a 16x16 group (2x2 tiles).  Workgroup ids are remapped so
+// that each of the eight XCDs (which receive workgroups round robin) renders a
+// contiguous band of groups and keeps its part of the volume in its own L2.
+//
+// Per lane the ray keeps its current element (box, step and Bezier block in
+// registers) and only descends the k-d forest (Alg. 1) when a sample leaves
+// it; since elements are half-open and tile the domain, a sample inside the
+// cached box has that element, so the element sequence equals the look-up's.
+//
+// Sample positions are exact FP32 operations (no contraction, RNE), matching
+// the documented ray model; evaluation, transfer function and compositing are
+// FP32 with fused multiply-adds.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+namespace {
+
+constexpr int kTile = 8;
+constexpr int kGroup = 16;            // pixels per workgroup side
+constexpr int kThreads = 256;
+constexpr int kMaxViews = LR_MAX_VIEWS_PER_LAUNCH;
+
+struct SceneK {
+  const float* box;
+  const void* bez;
+  const uint32_t* heads;
+  const lr_kdnode* nodes;
+  const float4* lut;
+  int64_t n_elem;
+  int64_t n_nodes;
+  int64_t stride;           // Bezier row length in coefficients
+  int32_t bx, by, bz;
+  float fbx, fby, fbz;
+  float vmin, inv_range, inv_xi, alpha_clamp, t_term;
+  int32_t n_fixed, max_samples;
+};
+
+struct ViewsK {
+  lr_view v[kMaxViews];
+  int64_t group_base[kMaxViews + 1];   // prefix sums of 16x16 groups
+  int32_t groups_x[kMaxViews];
+  int32_t n;
+};
+
+struct Ray {
+  float o[3], d[3];
+  float t0, t1;
+  bool hit;
+};
+
+// ---------------------------------------------------------------- ray model
+__device__ inline Ray make_ray(const lr_view& v, int i, int j) {
+#pragma clang fp contract(off)
+  Ray r;
+  const float W = (float)v.width, H = (float)v.height;
+  const float fi = (float)(2 * i + 1), fj = (float)(2 * j + 1);
+  const float sx = __fmul_rn(__fsub_rn(__fdiv_rn(fi, W), 1.0f), v.tx);
+  const float sy = __fmul_rn(__fsub_rn(1.0f, __fdiv_rn(fj, H)), v.ty);
+  if (v.proj == LR_PERSP) {
+    float dp[3];
+    for (int a = 0; a < 3; ++a)
+      dp[a] = __fadd_rn(__fadd_rn(v.fwd[a], __fmul_rn(sx, v.right[a])), __fmul_rn(sy, v.up[a]));
+    const float n2 = __fadd_rn(__fadd_rn(__fmul_rn(dp[0], dp[0]), __fmul_rn(dp[1], dp[1])), __fmul_rn(dp[2], dp[2]));
+    const float n = __fsqrt_rn(n2);
+    for (int a = 0; a < 3; ++a) {
+      r.d[a] = __fdiv_rn(dp[a], n);
+      r.o[a] = v.eye[a];
+    }
+  } else {
+    for (int a = 0; a < 3; ++a) {
+      r.o[a] = __fadd_rn(__fadd_rn(v.eye[a], __fmul_rn(sx, v.right[a])), __fmul_rn(sy, v.up[a]));
+      r.d[a] = v.fwd[a];
+    }
+  }
+  float t0 = 0.0f, t1 = INFINITY;
+  bool hit = true;
+  for (int a = 0; a < 3; ++a) {
+    if (r.d[a] != 0.0f) {
+      const float ta = __fdiv_rn(__fsub_rn(0.0f, r.o[a]), r.d[a]);
+      const float tb = __fdiv_rn(__fsub_rn(1.0f, r.o[a]), r.d[a]);
+      t0 = fmaxf(t0, fminf(ta, tb));
+      t1 = fminf(t1, fmaxf(ta, tb));
+    } else {
+      hit = hit && r.o[a] >= 0.0f && r.o[a] <= 1.0f;
+    }
+  }
+  r.t0 = t0;
+  r.t1 = t1;
+  r.hit = hit && t0 < t1;
+  return r;
+}
+
+__device__ inline void position(const Ray& r, float t, float p[3]) {
+#pragma clang fp contract(off)
+  for (int a = 0; a < 3; ++a) p[a] = fminf(fmaxf(__fadd_rn(r.o[a], __fmul_rn(t, r.d[a])), 0.0f), 1.0f);
+}
+
+__device__ inline bool inside(const float p[3], const float lo[3], const float hi[3]) {
+  bool in = true;
+  for (int a = 0; a < 3; ++a) in = in && lo[a] <= p[a] && (p[a] < hi[a] || (p[a] == 1.0f && hi[a] == 1.0f));
+  return in;
+}
+
+// ---------------------------------------------------------------- Alg. 1
+__device__ inline int32_t forest_lookup(const uint32_t* __restrict__ heads, const lr_kdnode* __restrict__ nodes,
+                                        int64_t n_nodes, int64_t n_elem, int32_t bx, int32_t by, int32_t bz,
+                                        float fbx, float fby, float fbz, const float p[3]) {
+  const int ix = min((int)(p[0] * fbx), bx - 1);
+  const int iy = min((int)(p[1] * fby), by - 1);
+  const int iz = min((int)(p[2] * fbz), bz - 1);
+  uint32_t r = heads[((int64_t)iz * by + iy) * bx + ix];
+  for (int guard = 0; guard < 256 && !(r & LR_LEAF); ++guard) {
+    if ((int64_t)r >= n_nodes) break;
+    const uint4 nd = reinterpret_cast<const uint4*>(nodes)[r];
+    const float split = __uint_as_float(nd.z);
+    const float v = nd.w == 0 ? p[0] : (nd.w == 1 ? p[1] : p[2]);
+    r = v < split ? nd.x : nd.y;
+  }
+  const int64_t e = (r & LR_LEAF) ? (int64_t)(r & ~LR_LEAF) : 0;
+  return e < n_elem ? (int32_t)e : 0;
+}
+
+// ---------------------------------------------------------------- Bezier blocks
+template <int NCF, typename CT>
+struct Coef;
+
+template <int NCF>
+struct Coef<NCF, float> {
+  static constexpr int N4 = (NCF + 3) / 4;
+  __device__ static inline void load(const void* bez, int64_t stride, int32_t e, float* c) {
+    const float4* r4 = reinterpret_cast<const float4*>(static_cast<const float*>(bez) + (int64_t)e * stride);
+#pragma unroll
+    for (int i = 0; i < N4; ++i) {
+      const float4 v = r4[i];
+      c[4 * i + 0] = v.x;
+      c[4 * i + 1] = v.y;
+      c[4 * i + 2] = v.z;
+      c[4 * i + 3] = v.w;
+    }
+  }
+  static constexpr int kRegs = 4 * N4;
+};
+
+template <int NCF>
+struct Coef<NCF, _Float16> {
+  static constexpr int N8 = (NCF + 7) / 8;
+  __device__ static inline void load(const void* bez, int64_t stride, int32_t e, float* c) {
+    const uint4* r8 = reinterpret_cast<const uint4*>(static_cast<const _Float16*>(bez) + (int64_t)e * stride);
+#pragma unroll
+    for (int i = 0; i < N8; ++i) {
+      const uint4 v = r8[i];
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        _Float16 lo, hi;
+        const unsigned short l = (unsigned short)(w[k] & 0xffffu), h = (unsigned short)(w[k] >> 16);
+        memcpy(&lo, &l, 2);
+        memcpy(&hi, &h, 2);
+        c[8 * i + 2 * k] = (float)lo;
+        c[8 * i + 2 * k + 1] = (float)hi;
+      }
+    }
+  }
+  static constexpr int kRegs = 8 * N8;
+};
+
+template <int P>
+__device__ inline void bernstein(float u, float b[P + 1]) {
+  const float v = 1.0f - u;
+  if constexpr (P == 1) {
+    b[0] = v;
+    b[1] = u;
+  } else if constexpr (P == 2) {
+    b[0] = v * v;
+    b[1] = 2.0f * u * v;
+    b[2] = u * u;
+  } else {
+    const float v2 = v * v, u2 = u * u;
+    b[0] = v2 * v;
+    b[1] = 3.0f * u * v2;
+    b[2] = 3.0f * u2 * v;
+    b[3] = u2 * u;
+  }
+}
+
+// sum_j c[j] Bx[jx] By[jy] Bz[jz] for one component (x fastest).
+template <int P>
+__device__ inline float contract(const float* c, const float* bx, const float* by, const float* bz) {
+  constexpr int Q = P + 1;
+  float acc = 0.0f;
+#pragma unroll
+  for (int kz = 0; kz < Q; ++kz) {
+    float ay = 0.0f;
+#pragma unroll
+    for (int jy = 0; jy < Q; ++jy) {
+      float ax = 0.0f;
+#pragma unroll
+      for (int ix = 0; ix < Q; ++ix) ax = fmaf(c[(kz * Q + jy) * Q + ix], bx[ix], ax);
+      ay = fmaf(ax, by[jy], ay);
+    }
+    acc = fmaf(ay, bz[kz], acc);
+  }
+  return acc;
+}
+
+// ---------------------------------------------------------------- transfer function
+struct TF {
+  float4 rgba;
+  float s;       // table position in [0, 255]
+  int i0, i1;
+  float w;
+  bool inside;   // value strictly inside (vmin, vmax): d s / d v != 0
+};
+
+__device__ inline TF transfer(const float4* lut, float v, float vmin, float inv_range) {
+  TF t;
+  float x = (v - vmin) * inv_range;
+  t.inside = x > 0.0f && x < 1.0f;
+  x = fminf(fmaxf(x, 0.0f), 1.0f);
+  t.s = x * 255.0f;
+  t.i0 = min((int)t.s, 255);
+  t.i1 = min(t.i0 + 1, 255);
+  t.w = t.s - (float)t.i0;
+  const float4 a = lut[t.i0], b = lut[t.i1];
+  t.rgba.x = fmaf(t.w, b.x - a.x, a.x);
+  t.rgba.y = fmaf(t.w, b.y - a.y, a.y);
+  t.rgba.z = fmaf(t.w, b.z - a.z, a.z);
+  t.rgba.w = fmaf(t.w, b.w - a.w, a.w);
+  return t;
+}
+
+// RGB of hue h in [0,1) at full saturation and value.
+__device__ inline void hsv_full(float h, float rgb[3]) {
+  const float h6 = h * 6.0f;
+  const float k = floorf(h6);
+  const float f = h6 - k;
+  int s = (int)k;
+  s = s >= 6 ? 0 : s;
+  const float q = 1.0f - f;
+  switch (s) {
+    case 0: rgb[0] = 1.0f; rgb[1] = f; rgb[2] = 0.0f; break;
+    case 1: rgb[0] = q; rgb[1] = 1.0f; rgb[2] = 0.0f; break;
+    case 2: rgb[0] = 0.0f; rgb[1] = 1.0f; rgb[2] = f; break;
+    case 3: rgb[0] = 0.0f; rgb[1] = q; rgb[2] = 1.0f; break;
+    case 4: rgb[0] = f; rgb[1] = 0.0f; rgb[2] = 1.0f; break;
+    default: rgb[0] = 1.0f; rgb[1] = 0.0f; rgb[2] = q; break;
+  }
+}
+
+__device__ inline float hue_of(float fx, float fy) {
+  if (fx == 0.0f && fy == 0.0f) return 0.0f;
+  float h = atan2f(fy, fx) * 0.15915494309189535f;
+  if (h < 0.0f) h += 1.0f;
+  return h >= 1.0f ? 0.0f : h;
+}
+
+// ---------------------------------------------------------------- the march
+// Everything a sample produced that a visitor may need.
+template <int P>
+struct Sample {
+  int32_t e;
+  float t, ds;            // sample parameter and composited segment length
+  float bx[P + 1], by[P + 1], bz[P + 1];
+  float csrc[3];
+  float alpha;            // after the clamp
+  bool clamped;
+  TF tf;
+};
+
+template <int P, int NCOMP, typename CT, int MODE, int COLOR, class Visitor>
+__device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, Visitor& vis) {
+  constexpr int NB = (P + 1) * (P + 1) * (P + 1);
+  constexpr int NCF = NCOMP * NB;
+  float c[Coef<NCF, CT>::kRegs];
+  float lo[3] = {2.0f, 2.0f, 2.0f}, hi[3] = {-1.0f, -1.0f, -1.0f}, inv[3] = {0.0f, 0.0f, 0.0f};
+  float ds_e = 0.0f;
+  int32_t e = -1;
+  const float step_scale = 1.0f / (float)(1 << P);
+  float dsf = 0.0f;
+  if (MODE == LR_STEP_FIXED) dsf = __fdiv_rn(__fsub_rn(r.t1, r.t0), (float)s.n_fixed);
+  float t = r.t0;
+  int n = 0;
+  for (;;) {
+    float ts;
+    if (MODE == LR_STEP_FIXED) {
+      if (n >= s.n_fixed) break;
+      ts = __fadd_rn(r.t0, __fmul_rn((float)n + 0.5f, dsf));
+    } else {
+      ts = t;
+    }
+    float p[3];
+    position(r, ts, p);
+    if (!inside(p, lo, hi)) {
+      e = forest_lookup(s.heads, s.nodes, s.n_nodes, s.n_elem, s.bx, s.by, s.bz, s.fbx, s.fby, s.fbz, p);
+      const float2* b2 = reinterpret_cast<const float2*>(s.box + 6 * (int64_t)e);
+      const float2 b01 = b2[0], b23 = b2[1], b45 = b2[2];
+      lo[0] = b01.x; lo[1] = b01.y; lo[2] = b23.x;
+      hi[0] = b23.y; hi[1] = b45.x; hi[2] = b45.y;
+      const float side = fminf(fminf(__fsub_rn(hi[0], lo[0]), __fsub_rn(hi[1], lo[1])), __fsub_rn(hi[2], lo[2]));
+      ds_e = __fmul_rn(side, step_scale);
+      for (int a = 0; a < 3; ++a) inv[a] = 1.0f / (hi[a] - lo[a]);
+      Coef<NCF, CT>::load(s.bez, s.stride, e, c);
+    }
+    Sample<P> sm;
+    sm.e = e;
+    sm.t = ts;
+    float ds;
+    if (MODE == LR_STEP_FIXED) {
+      ds = dsf;
+      sm.ds = dsf;
+    } else {
+      ds = ds_e;
+      sm.ds = fminf(ds_e, __fsub_rn(r.t1, ts));
+    }
+    const float ux = fminf(fmaxf((p[0] - lo[0]) * inv[0], 0.0f), 1.0f);
+    const float uy = fminf(fmaxf((p[1] - lo[1]) * inv[1], 0.0f), 1.0f);
+    const float uz = fminf(fmaxf((p[2] - lo[2]) * inv[2], 0.0f), 1.0f);
+    bernstein<P>(ux, sm.bx);
+    bernstein<P>(uy, sm.by);
+    bernstein<P>(uz, sm.bz);
+    if constexpr (COLOR == LR_COLOR_HUE) {
+      const float fx = contract<P>(c, sm.bx, sm.by, sm.bz);
+      const float fy = contract<P>(c + NB, sm.bx, sm.by, sm.bz);
+      const float fz = contract<P>(c + 2 * NB, sm.bx, sm.by, sm.bz);
+      const float vm = sqrtf(fmaf(fx, fx, fmaf(fy, fy, fz * fz)));
+      sm.tf = transfer(lut, vm, s.vmin, s.inv_range);
+      hsv_full(hue_of(fx, fy), sm.csrc);
+    } else {
+      const float v = contract<P>(c, sm.bx, sm.by, sm.bz);
+      sm.tf = transfer(lut, v, s.vmin, s.inv_range);
+      sm.csrc[0] = sm.tf.rgba.x;
+      sm.csrc[1] = sm.tf.rgba.y;
+      sm.csrc[2] = sm.tf.rgba.z;
+    }
+    sm.clamped = sm.tf.rgba.w > s.alpha_clamp;
+    sm.alpha = fminf(sm.tf.rgba.w, s.alpha_clamp);
+    ++n;
+    const bool stop = vis.sample(s, sm);
+    if (stop || n >= s.max_samples) break;
+    if (MODE == LR_STEP_ADAPTIVE) {
+      t = __fadd_rn(ts, ds);
+      if (!(t < r.t1)) break;
+    }
+  }
+  vis.finish(n);
+}
+
+// Alg. 2 with the transmittance carried multiplicatively:
+// a = 1 - (1 - alpha)^(ds/xi) = -expm1(log1p(-alpha) ds/xi), C += T a C_src, T *= 1 - a.
+struct Composite {
+  float C[3] = {0.0f, 0.0f, 0.0f};
+  float T = 1.0f;
+  __device__ inline float opacity(const SceneK& s, float alpha, float ds) const {
+    return -expm1f(log1pf(-alpha) * (ds * s.inv_xi));
+  }
+  template <int P>
+  __device__ inline bool sample(const SceneK& s, const Sample<P>& sm) {
+    const float a = opacity(s, sm.alpha, sm.ds);
+    const float w = T * a;
+    C[0] = fmaf(w, sm.csrc[0], C[0]);
+    C[1] = fmaf(w, sm.csrc[1], C[1]);
+    C[2] = fmaf(w, sm.csrc[2], C[2]);
+    T = fmaf(-T, a, T);
+    return T <= s.t_term;
+  }
+  __device__ inline void finish(int) {}
+};
+
+struct TraceVisitor : Composite {
+  float* t_out;
+  int32_t* e_out;
+  float* ds_out;
+  int32_t max_out;
+  int32_t k = 0;
+  template <int P>
+  __device__ inline bool sample(const SceneK& s, const Sample<P>& sm) {
+    if (k < max_out) {
+      t_out[k] = sm.t;
+      e_out[k] = sm.e;
+      ds_out[k] = sm.ds;
+    }
+    ++k;
+    return Composite::sample<P>(s, sm);
+  }
+};
+
+__device__ inline int64_t remap_xcd(int64_t bid, int64_t nblk) {
+  // Workgroups are dealt to the 8 XCDs round robin; give XCD x the contiguous
+  // range [x*q + min(x, r), ...) of logical groups.
+  const int64_t x = bid & 7, k = bid >> 3, q = nblk >> 3, rr = nblk & 7;
+  return x * q + (x < rr ? x : rr) + k;
+}
+
+__device__ inline bool locate(const ViewsK& vk, int64_t g, int& v, int& px, int& py) {
+  v = 0;
+  while (v + 1 < vk.n && g >= vk.group_base[v + 1]) ++v;
+  const int64_t lg = g - vk.group_base[v];
+  const int gx = (int)(lg % vk.groups_x[v]), gy = (int)(lg / vk.groups_x[v]);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  px = gx * kGroup + (wave & 1) * kTile + (lane & 7);
+  py = gy * kGroup + (wave >> 1) * kTile + (lane >> 3);
+  return px < vk.v[v].width && py < vk.v[v].height;
+}
+
+template <int P, int NCOMP, typename CT, int MODE, int COLOR>
+__global__ __launch_bounds__(kThreads) void render_kernel(const SceneK s, const ViewsK vk, float4* __restrict__ rgba,
+                                                         uint32_t* __restrict__ nsamples) {
+  __shared__ float4 lut[256];
+  lut[threadIdx.x] = s.lut[threadIdx.x];
+  __syncthreads();
+  const int64_t g = remap_xcd(blockIdx.x, gridDim.x);
+  int v, px, py;
+  if (!locate(vk, g, v, px, py)) return;
+  const lr_view& view = vk.v[v];
+  const int64_t o = view.out_offset + (int64_t)py * view.width + px;
+  const Ray r = make_ray(view, px, py);
+  struct Counter : Composite {
+    int n = 0;
+    __device__ inline void finish(int k) { n = k; }
+  } vis;
+  if (r.hit) march<P, NCOMP, CT, MODE, COLOR>(s, r, lut, vis);
+  rgba[o] = make_float4(vis.C[0], vis.C[1], vis.C[2], 1.0f - vis.T);
+  if (nsamples) nsamples[o] = (uint32_t)vis.n;
+}
+
+template <int P, int NCOMP, typename CT, int MODE, int COLOR>
+__global__ __launch_bounds__(64) void trace_kernel(const SceneK s, const lr_view view, const int32_t* __restrict__ pix,
+                                                   int64_t n, int32_t max_out, float* t_out, int32_t* e_out,
+                                                   float* ds_out, int32_t* count) {
+  __shared__ float4 lut[256];
+  for (int i = threadIdx.x; i < 256; i += 64) lut[i] = s.lut[i];
+  __syncthreads();
+  const int64_t k = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (k >= n) return;
+  const int i = pix[2 * k], j = pix[2 * k + 1];
+  TraceVisitor vis;
+  vis.t_out = t_out + k * max_out;
+  vis.e_out = e_out + k * max_out;
+  vis.ds_out = ds_out + k * max_out;
+  vis.max_out = max_out;
+  int taken = 0;
+  if (i >= 0 && j >= 0 && i < view.width && j < view.height) {
+    const Ray r = make_ray(view, i, j);
+    if (r.hit) march<P, NCOMP, CT, MODE, COLOR>(s, r, lut, vis);
+    taken = vis.k;
+  }
+  count[k] = taken;
+}
+
+__global__ void lookup_kernel(const uint32_t* __restrict__ heads, const lr_kdnode* __restrict__ nodes, int64_t n_nodes,
+                              int64_t n_elem, int32_t bx, int32_t by, int32_t bz, const float* __restrict__ pts, int64_t n,
+                              int32_t* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  float p[3];
+  for (int a = 0; a < 3; ++a) p[a] = fminf(fmaxf(pts[3 * k + a], 0.0f), 1.0f);
+  out[k] = forest_lookup(heads, nodes, n_nodes, n_elem, bx, by, bz, (float)bx, (float)by, (float)bz, p);
+}
+
+// ---------------------------------------------------------------- adjoint
+// Per sample i with T_i the transmittance before it, a_i its opacity and
+// C_i = C after it:  dL/dC_src = g_C T_i a_i;
+// dL/da_i = g_C . (T_i C_src - (C_final - C_i)/(1 - a_i)) + g_alpha T_final/(1 - a_i);
+// da/dalpha = (ds/xi)(1 - a)/(1 - alpha) (0 if clamped); then through the table
+// interpolation (LUT rows i0, i1) and s = 255 (v - vmin)/(vmax - vmin) into the
+// Bezier coefficients of the sample's element (dv/dC_j = B_j(u)).  Gradients of
+// consecutive samples in one element are summed in registers and flushed
+// with atomics when the element changes; table gradients go to LDS first.
+template <int P>
+struct Adjoint : Composite {
+  static constexpr int NB = (P + 1) * (P + 1) * (P + 1);
+  float Cfin[3];
+  float Tfin;
+  float gC[3];
+  float gA;
+  float* gbez;
+  int64_t stride;
+  float* glut_s;          // LDS [256][4]
+  float range_scale;      // 255 / (vmax - vmin)
+  const float4* lut;
+  int32_t cur = -1;
+  float acc[NB];
+
+  __device__ inline void flush() {
+    if (cur >= 0) {
+      float* row = gbez + (int64_t)cur * stride;
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        if (acc[j] != 0.0f) unsafeAtomicAdd(row + j, acc[j]);
+    }
+  }
+
+  __device__ inline bool sample(const SceneK& s, const Sample<P>& sm) {
+    const float a = opacity(s, sm.alpha, sm.ds);
+    const float w = T * a;
+    float Cn[3];
+    for (int ch = 0; ch < 3; ++ch) Cn[ch] = fmaf(w, sm.csrc[ch], C[ch]);
+    const float om = 1.0f - a;
+    float g_a = gA * Tfin / om;
+    float g_x[4];
+    for (int ch = 0; ch < 3; ++ch) {
+      g_x[ch] = gC[ch] * w;
+      g_a = fmaf(gC[ch], T * sm.csrc[ch] - (Cfin[ch] - Cn[ch]) / om, g_a);
+    }
+    const float r = sm.ds * s.inv_xi;
+    g_x[3] = sm.clamped ? 0.0f : g_a * r * om / (1.0f - sm.alpha);
+    // table rows
+    const float w1 = sm.tf.w, w0 = 1.0f - sm.tf.w;
+    for (int ch = 0; ch < 4; ++ch) {
+      if (g_x[ch] != 0.0f) {
+        atomicAdd(&glut_s[4 * sm.tf.i0 + ch], w0 * g_x[ch]);
+        atomicAdd(&glut_s[4 * sm.tf.i1 + ch], w1 * g_x[ch]);
+      }
+    }
+    const float4 l0 = lut[sm.tf.i0], l1 = lut[sm.tf.i1];
+    float g_s = g_x[0] * (l1.x - l0.x);
+    g_s = fmaf(g_x[1], l1.y - l0.y, g_s);
+    g_s = fmaf(g_x[2], l1.z - l0.z, g_s);
+    g_s = fmaf(g_x[3], l1.w - l0.w, g_s);
+    const float g_v = sm.tf.inside ? g_s * range_scale : 0.0f;
+    if (sm.e != cur) {
+      flush();
+      cur = sm.e;
+#pragma unroll
+      for (int j = 0; j < NB; ++j) acc[j] = 0.0f;
+    }
+    constexpr int Q = P + 1;
+#pragma unroll
+    for (int kz = 0; kz < Q; ++kz)
+#pragma unroll
+      for (int jy = 0; jy < Q; ++jy) {
+        const float gyz = g_v * sm.by[jy] * sm.bz[kz];
+#pragma unroll
+        for (int ix = 0; ix < Q; ++ix) acc[(kz * Q + jy) * Q + ix] = fmaf(gyz, sm.bx[ix], acc[(kz * Q + jy) * Q + ix]);
+      }
+    C[0] = Cn[0];
+    C[1] = Cn[1];
+    C[2] = Cn[2];
+    T = fmaf(-T, a, T);
+    return T <= s.t_term;
+  }
+  __device__ inline void finish(int) { flush(); }
+};
+
+template <int P, int MODE>
+__global__ __launch_bounds__(kThreads) void backward_kernel(const SceneK s, const ViewsK vk, const float4* __restrict__ fwd,
+                                                           const float4* __restrict__ grad, float* __restrict__ gbez,
+                                                           float* __restrict__ glut) {
+  __shared__ float4 lut[256];
+  __shared__ float glut_s[1024];
+  lut[threadIdx.x] = s.lut[threadIdx.x];
+  for (int i = threadIdx.x; i < 1024; i += kThreads) glut_s[i] = 0.0f;
+  __syncthreads();
+  const int64_t g = remap_xcd(blockIdx.x, gridDim.x);
+  int v, px, py;
+  if (locate(vk, g, v, px, py)) {
+    const lr_view& view = vk.v[v];
+    const int64_t o = view.out_offset + (int64_t)py * view.width + px;
+    const Ray r = make_ray(view, px, py);
+    const float4 gr = grad[o];
+    if (r.hit && (gr.x != 0.0f || gr.y != 0.0f || gr.z != 0.0f || gr.w != 0.0f)) {
+      const float4 f = fwd[o];
+      Adjoint<P> vis;
+      vis.Cfin[0] = f.x;
+      vis.Cfin[1] = f.y;
+      vis.Cfin[2] = f.z;
+      vis.Tfin = 1.0f - f.w;
+      vis.gC[0] = gr.x;
+      vis.gC[1] = gr.y;
+      vis.gC[2] = gr.z;
+      vis.gA = gr.w;
+      vis.gbez = gbez;
+      vis.stride = s.stride;
+      vis.glut_s = glut_s;
+      vis.range_scale = 255.0f * s.inv_range;
+      vis.lut = lut;
+      march<P, 1, float, MODE, LR_COLOR_LUT>(s, r, lut, vis);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 1024; i += kThreads)
+    if (glut_s[i] != 0.0f) unsafeAtomicAdd(glut + i, glut_s[i]);
+}
+
+// ---------------------------------------------------------------- host side
+lr_status make_scene(const lr_scene* sc, SceneK& s, bool need_forest = true) {
+  using lrvr::fail;
+  if (!sc) return fail(LR_EINVAL, "null scene");
+  const int P = sc->p[0];
+  if (sc->p[1] != P || sc->p[2] != P || P < 1 || P > 3)
+    return fail(LR_EINVAL, "render kernels take equal degrees p1 = p2 = p3 in [1,3]");
+  if (!((sc->ncomp == 1 && sc->color_mode == LR_COLOR_LUT) || (sc->ncomp == 3 && sc->color_mode == LR_COLOR_HUE)))
+    return fail(LR_EINVAL, "ncomp/color_mode must be 1/LR_COLOR_LUT or 3/LR_COLOR_HUE");
+  if (sc->bezier_dtype != LR_F32 && sc->bezier_dtype != LR_F16)
+    return fail(LR_EINVAL, "bezier_dtype must be LR_F32 or LR_F16");
+  if (sc->step_mode != LR_STEP_FIXED && sc->step_mode != LR_STEP_ADAPTIVE) return fail(LR_EINVAL, "bad step_mode");
+  if (sc->step_mode == LR_STEP_FIXED && sc->n_fixed_steps < 1) return fail(LR_EINVAL, "n_fixed_steps < 1");
+  if (sc->max_samples < 1) return fail(LR_EINVAL, "max_samples < 1");
+  if (!sc->elem_box || !sc->bezier || !sc->lut || (need_forest && (!sc->heads || (!sc->nodes && sc->n_nodes > 0))))
+    return fail(LR_EINVAL, "null device array in the scene");
+  if (sc->n_elem <= 0 || sc->n_elem >= (int64_t)LR_LEAF || sc->n_nodes < 0) return fail(LR_EINVAL, "bad n_elem / n_nodes");
+  for (int d = 0; d < 3; ++d)
+    if (!lrvr::is_pow2(sc->blocks[d]) || sc->blocks[d] > 512) return fail(LR_ENOTPOW2, "blocks must be powers of two <= 512");
+  if (!(sc->vmax > sc->vmin) || !(sc->xi > 0.0f) || !(sc->alpha_clamp < 1.0f) || !(sc->alpha_clamp >= 0.0f) ||
+      !(sc->term_alpha > 0.0f && sc->term_alpha <= 1.0f))
+    return fail(LR_EINVAL, "need vmax > vmin, xi > 0, 0 <= alpha_clamp < 1, 0 < term_alpha <= 1");
+  s.box = sc->elem_box;
+  s.bez = sc->bezier;
+  s.heads = sc->heads;
+  s.nodes = sc->nodes;
+  s.lut = reinterpret_cast<const float4*>(sc->lut);
+  s.n_elem = sc->n_elem;
+  s.n_nodes = sc->n_nodes;
+  s.stride = lr_bezier_stride(sc->p, sc->ncomp, sc->bezier_dtype);
+  s.bx = sc->blocks[0];
+  s.by = sc->blocks[1];
+  s.bz = sc->blocks[2];
+  s.fbx = (float)s.bx;
+  s.fby = (float)s.by;
+  s.fbz = (float)s.bz;
+  s.vmin = sc->vmin;
+  s.inv_range = (float)(1.0 / ((double)sc->vmax - (double)sc->vmin));
+  s.inv_xi = (float)(1.0 / (double)sc->xi);
+  s.alpha_clamp = sc->alpha_clamp;
+  s.t_term = (float)(1.0 - (double)sc->term_alpha);
+  s.n_fixed = sc->n_fixed_steps;
+  s.max_samples = sc->max_samples;
+  return LR_OK;
+}
+
+lr_status check_view(const lr_view& v) {
+  if (v.proj != LR_PERSP && v.proj != LR_ORTHO) return lrvr::fail(LR_EINVAL, "view: bad projection");
+  if (v.width < 1 || v.height < 1 || v.width > (1 << 16) || v.height > (1 << 16) || v.out_offset < 0)
+    return lrvr::fail(LR_EINVAL, "view: size must be 1..65536 and out_offset >= 0");
+  const float* f = v.eye;
+  for (int i = 0; i < 14; ++i)
+    if (!std::isfinite(f[i])) return lrvr::fail(LR_EINVAL, "view: non-finite camera value");
+  return LR_OK;
+}
+
+// Packs up to kMaxViews views; returns the number of workgroups.
+int64_t pack_views(const lr_view* views, int32_t n, ViewsK& vk) {
+  std::memset(&vk, 0, sizeof vk);
+  vk.n = n;
+  vk.group_base[0] = 0;
+  for (int i = 0; i < n; ++i) {
+    vk.v[i] = views[i];
+    vk.groups_x[i] = (views[i].width + kGroup - 1) / kGroup;
+    const int64_t gy = (views[i].height + kGroup - 1) / kGroup;
+    vk.group_base[i + 1] = vk.group_base[i] + (int64_t)vk.groups_x[i] * gy;
+  }
+  return vk.group_base[n];
+}
+
+template <int P, int NCOMP, typename CT, int MODE, int COLOR>
+void launch_render(const SceneK& s, const ViewsK& vk, int64_t nblk, float* rgba, uint32_t* ns, hipStream_t st) {
+  hipLaunchKernelGGL((render_kernel<P, NCOMP, CT, MODE, COLOR>), dim3((unsigned)nblk), dim3(kThreads), 0, st, s, vk,
+                     reinterpret_cast<float4*>(rgba), ns);
+}
+
+template <int P, int NCOMP, int COLOR>
+void dispatch_dtype_mode(const lr_scene* sc, const SceneK& s, const ViewsK& vk, int64_t nblk, float* rgba, uint32_t* ns,
+                         hipStream_t st) {
+  const bool f16 = sc->bezier_dtype == LR_F16;
+  if (sc->step_mode == LR_STEP_FIXED) {
+    if (f16) launch_render<P, NCOMP, _Float16, LR_STEP_FIXED, COLOR>(s, vk, nblk, rgba, ns, st);
+    else launch_render<P, NCOMP, float, LR_STEP_FIXED, COLOR>(s, vk, nblk, rgba, ns, st);
+  } else {
+    if (f16) launch_render<P, NCOMP, _Float16, LR_STEP_ADAPTIVE, COLOR>(s, vk, nblk, rgba, ns, st);
+    else launch_render<P, NCOMP, float, LR_STEP_ADAPTIVE, COLOR>(s, vk, nblk, rgba, ns, st);
+  }
+}
+
+template <int P>
+void dispatch_render(const lr_scene* sc, const SceneK& s, const ViewsK& vk, int64_t nblk, float* rgba, uint32_t* ns,
+                     hipStream_t st) {
+  if (sc->ncomp == 1) dispatch_dtype_mode<P, 1, LR_COLOR_LUT>(sc, s, vk, nblk, rgba, ns, st);
+  else dispatch_dtype_mode<P, 3, LR_COLOR_HUE>(sc, s, vk, nblk, rgba, ns, st);
+}
+
+template <int P, int NCOMP, typename CT, int MODE, int COLOR>
+void launch_trace(const SceneK& s, const lr_view& v, const int32_t* pix, int64_t n, int32_t m, float* t, int32_t* e,
+                  float* ds, int32_t* cnt, hipStream_t st) {
+  hipLaunchKernelGGL((trace_kernel<P, NCOMP, CT, MODE, COLOR>), dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, s, v,
+                     pix, n, m, t, e, ds, cnt);
+}
+
+template <int P>
+void dispatch_trace(const lr_scene* sc, const SceneK& s, const lr_view& v, const int32_t* pix, int64_t n, int32_t m,
+                    float* t, int32_t* e, float* ds, int32_t* cnt, hipStream_t st) {
+  const bool f16 = sc->bezier_dtype == LR_F16, fixed = sc->step_mode == LR_STEP_FIXED;
+#define LR_TRACE(NC, COL)                                                                                  \
+  if (fixed) {                                                                                             \
+    if (f16) launch_trace<P, NC, _Float16, LR_STEP_FIXED, COL>(s, v, pix, n, m, t, e, ds, cnt, st);        \
+    else launch_trace<P, NC, float, LR_STEP_FIXED, COL>(s, v, pix, n, m, t, e, ds, cnt, st);               \
+  } else {                                                                                                 \
+    if (f16) launch_trace<P, NC, _Float16, LR_STEP_ADAPTIVE, COL>(s, v, pix, n, m, t, e, ds, cnt, st);     \
+    else launch_trace<P, NC, float, LR_STEP_ADAPTIVE, COL>(s, v, pix, n, m, t, e, ds, cnt, st);            \
+  }
+  if (sc->ncomp == 1) {
+    LR_TRACE(1, LR_COLOR_LUT)
+  } else {
+    LR_TRACE(3, LR_COLOR_HUE)
+  }
+#undef LR_TRACE
+}
+
+}  // namespace
+
+using lrvr::fail;
+
+LR_API lr_status lr_render(const lr_scene* sc, const lr_view* views, int32_t n_views, float* rgba, uint32_t* nsamples,
+                           void* stream) {
+  SceneK s;
+  lr_status st = make_scene(sc, s);
+  if (st != LR_OK) return st;
+  if (!views || n_views < 1 || !rgba) return fail(LR_EINVAL, "lr_render: need views, n_views >= 1 and rgba");
+  for (int i = 0; i < n_views; ++i)
+    if ((st = check_view(views[i])) != LR_OK) return st;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  for (int base = 0; base < n_views; base += kMaxViews) {
+    const int cnt = n_views - base < kMaxViews ? n_views - base : kMaxViews;
+    ViewsK vk;
+    const int64_t nblk = pack_views(views + base, cnt, vk);
+    if (nblk <= 0 || nblk > 0x7fffffff) return fail(LR_EINVAL, "lr_render: image too large for one launch");
+    switch (sc->p[0]) {
+      case 1: dispatch_render<1>(sc, s, vk, nblk, rgba, nsamples, hs); break;
+      case 2: dispatch_render<2>(sc, s, vk, nblk, rgba, nsamples, hs); break;
+      default: dispatch_render<3>(sc, s, vk, nblk, rgba, nsamples, hs); break;
+    }
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return fail(LR_EHIP, "lr_render: %s", hipGetErrorString(err));
+  }
+  return LR_OK;
+}
+
+LR_API lr_status lr_trace_rays(const lr_scene* sc, const lr_view* view, const int32_t* pix, int64_t n, int32_t max_out,
+                               float* t_out, int32_t* elem_out, float* ds_out, int32_t* count, void* stream) {
+  SceneK s;
+  lr_status st = make_scene(sc, s);
+  if (st != LR_OK) return st;
+  if (!view || !pix || n < 1 || max_out < 1 || !t_out || !elem_out || !ds_out || !count)
+    return fail(LR_EINVAL, "lr_trace_rays: null pointer or empty request");
+  if (n > ((int64_t)1 << 30)) return fail(LR_EINVAL, "lr_trace_rays: too many rays");
+  if ((st = check_view(*view)) != LR_OK) return st;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  switch (sc->p[0]) {
+    case 1: dispatch_trace<1>(sc, s, *view, pix, n, max_out, t_out, elem_out, ds_out, count, hs); break;
+    case 2: dispatch_trace<2>(sc, s, *view, pix, n, max_out, t_out, elem_out, ds_out, count, hs); break;
+    default: dispatch_trace<3>(sc, s, *view, pix, n, max_out, t_out, elem_out, ds_out, count, hs); break;
+  }
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return fail(LR_EHIP, "lr_trace_rays: %s", hipGetErrorString(err));
+  return LR_OK;
+}
+
+LR_API lr_status lr_lookup(const uint32_t* heads, const lr_kdnode* nodes, int64_t n_nodes, const int32_t blocks[3],
+                           int64_t n_elem, const float* points, int64_t n, int32_t* elem_out, void* stream) {
+  if (!heads || !blocks || !points || !elem_out || n < 0 || n_nodes < 0 || (n_nodes > 0 && !nodes))
+    return fail(LR_EINVAL, "lr_lookup: null pointer or negative size");
+  if (n_elem <= 0 || n_elem >= (int64_t)LR_LEAF) return fail(LR_EINVAL, "lr_lookup: bad n_elem");
+  for (int d = 0; d < 3; ++d)
+    if (!lrvr::is_pow2(blocks[d]) || blocks[d] > 512) return fail(LR_ENOTPOW2, "lr_lookup: blocks must be powers of two <= 512");
+  if (n == 0) return LR_OK;
+  if (n > ((int64_t)1 << 40)) return fail(LR_EINVAL, "lr_lookup: too many points");
+  const int64_t nblk = (n + 255) / 256;
+  hipLaunchKernelGGL(lookup_kernel, dim3((unsigned)nblk), dim3(256), 0, static_cast<hipStream_t>(stream), heads, nodes,
+                     n_nodes, n_elem, blocks[0], blocks[1], blocks[2], points, n, elem_out);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return fail(LR_EHIP, "lr_lookup: %s", hipGetErrorString(err));
+  return LR_OK;
+}
+
+LR_API lr_status lr_render_backward(const lr_scene* sc, const lr_view* views, int32_t n_views, const float* rgba_fwd,
+                                    const float* grad_rgba, float* grad_bezier, float* grad_lut, void* stream) {
+  SceneK s;
+  lr_status st = make_scene(sc, s);
+  if (st != LR_OK) return st;
+  if (sc->ncomp != 1 || sc->color_mode != LR_COLOR_LUT || sc->bezier_dtype != LR_F32)
+    return fail(LR_EINVAL, "lr_render_backward: scalar fields with FP32 blocks only");
+  if (!views || n_views < 1 || !rgba_fwd || !grad_rgba || !grad_bezier || !grad_lut)
+    return fail(LR_EINVAL, "lr_render_backward: null pointer or no views");
+  for (int i = 0; i < n_views; ++i)
+    if ((st = check_view(views[i])) != LR_OK) return st;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  for (int base = 0; base < n_views; base += kMaxViews) {
+    const int cnt = n_views - base < kMaxViews ? n_views - base : kMaxViews;
+    ViewsK vk;
+    const int64_t nblk = pack_views(views + base, cnt, vk);
+    if (nblk <= 0 || nblk > 0x7fffffff) return fail(LR_EINVAL, "lr_render_backward: image too large");
+    const dim3 grid((unsigned)nblk), blk(kThreads);
+    const float4* f = reinterpret_cast<const float4*>(rgba_fwd);
+    const float4* g = reinterpret_cast<const float4*>(grad_rgba);
+    const bool fixed = sc->step_mode == LR_STEP_FIXED;
+#define LR_BWD(PP)                                                                                              \
+  if (fixed) hipLaunchKernelGGL((backward_kernel<PP, LR_STEP_FIXED>), grid, blk, 0, hs, s, vk, f, g, grad_bezier, grad_lut); \
+  else hipLaunchKernelGGL((backward_kernel<PP, LR_STEP_ADAPTIVE>), grid, blk, 0, hs, s, vk, f, g, grad_bezier, grad_lut);
+    switch (sc->p[0]) {
+      case 1: LR_BWD(1) break;
+      case 2: LR_BWD(2) break;
+      default: LR_BWD(3) break;
+    }
+#undef LR_BWD
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return fail(LR_EHIP, "lr_render_backward: %s", hipGetErrorString(err));
+  }
+  return LR_OK;
+}

@@ -20,5 +20,5 @@ def workload(name, **kw):
     import lrgen
     key = (name, tuple(sorted(kw.items())))
     if key not in _CACHE:
-        _CACHE[key] = getattr(lrgen, name)(**kw)
+        _CACHE[key] = lrgen.cached(name, **kw)
     return _CACHE[key]
