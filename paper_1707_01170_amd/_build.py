@@ -15,8 +15,9 @@ HIPCC_FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared", "-fvisibility=hidden",
     # packed FP32 instructions stay off (they have given wrong results on these parts)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # sample positions rely on uncontracted, correctly rounded FP32 operations
-    "-ffp-contract=fast-honor-pragmas", "-fhip-fp32-correctly-rounded-divide-sqrt",
+    # no implicit contraction: sample positions are exact FP32 operation sequences;
+    # fused multiply-adds are written as fmaf where wanted
+    "-ffp-contract=off", "-fhip-fp32-correctly-rounded-divide-sqrt",
     "-Wall", "-Wno-unused-result",
 ]
 

@@ -11,9 +11,9 @@
 // it; since elements are half-open and tile the domain, a sample inside the
 // cached box has that element, so the element sequence equals the look-up's.
 //
-// Sample positions are exact FP32 operations (no contraction, RNE), matching
-// the documented ray model; evaluation, transfer function and compositing are
-// FP32 with fused multiply-adds.
+// The library is compiled without floating-point contraction, so sample
+// positions are exact sequences of IEEE FP32 operations (the documented ray
+// model); evaluation, transfer function and compositing use explicit fmaf.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -59,25 +59,24 @@ struct Ray {
 
 // ---------------------------------------------------------------- ray model
 __device__ inline Ray make_ray(const lr_view& v, int i, int j) {
-#pragma clang fp contract(off)
+  // Built with -ffp-contract=off: each operator below is one IEEE FP32
+  // operation rounded to nearest, / and sqrt correctly rounded.
   Ray r;
   const float W = (float)v.width, H = (float)v.height;
   const float fi = (float)(2 * i + 1), fj = (float)(2 * j + 1);
-  const float sx = __fmul_rn(__fsub_rn(__fdiv_rn(fi, W), 1.0f), v.tx);
-  const float sy = __fmul_rn(__fsub_rn(1.0f, __fdiv_rn(fj, H)), v.ty);
+  const float sx = (fi / W - 1.0f) * v.tx;
+  const float sy = (1.0f - fj / H) * v.ty;
   if (v.proj == LR_PERSP) {
     float dp[3];
-    for (int a = 0; a < 3; ++a)
-      dp[a] = __fadd_rn(__fadd_rn(v.fwd[a], __fmul_rn(sx, v.right[a])), __fmul_rn(sy, v.up[a]));
-    const float n2 = __fadd_rn(__fadd_rn(__fmul_rn(dp[0], dp[0]), __fmul_rn(dp[1], dp[1])), __fmul_rn(dp[2], dp[2]));
-    const float n = __fsqrt_rn(n2);
+    for (int a = 0; a < 3; ++a) dp[a] = (v.fwd[a] + sx * v.right[a]) + sy * v.up[a];
+    const float n = __builtin_sqrtf((dp[0] * dp[0] + dp[1] * dp[1]) + dp[2] * dp[2]);
     for (int a = 0; a < 3; ++a) {
-      r.d[a] = __fdiv_rn(dp[a], n);
+      r.d[a] = dp[a] / n;
       r.o[a] = v.eye[a];
     }
   } else {
     for (int a = 0; a < 3; ++a) {
-      r.o[a] = __fadd_rn(__fadd_rn(v.eye[a], __fmul_rn(sx, v.right[a])), __fmul_rn(sy, v.up[a]));
+      r.o[a] = (v.eye[a] + sx * v.right[a]) + sy * v.up[a];
       r.d[a] = v.fwd[a];
     }
   }
@@ -85,8 +84,8 @@ __device__ inline Ray make_ray(const lr_view& v, int i, int j) {
   bool hit = true;
   for (int a = 0; a < 3; ++a) {
     if (r.d[a] != 0.0f) {
-      const float ta = __fdiv_rn(__fsub_rn(0.0f, r.o[a]), r.d[a]);
-      const float tb = __fdiv_rn(__fsub_rn(1.0f, r.o[a]), r.d[a]);
+      const float ta = (0.0f - r.o[a]) / r.d[a];
+      const float tb = (1.0f - r.o[a]) / r.d[a];
       t0 = fmaxf(t0, fminf(ta, tb));
       t1 = fminf(t1, fmaxf(ta, tb));
     } else {
@@ -100,8 +99,7 @@ __device__ inline Ray make_ray(const lr_view& v, int i, int j) {
 }
 
 __device__ inline void position(const Ray& r, float t, float p[3]) {
-#pragma clang fp contract(off)
-  for (int a = 0; a < 3; ++a) p[a] = fminf(fmaxf(__fadd_rn(r.o[a], __fmul_rn(t, r.d[a])), 0.0f), 1.0f);
+  for (int a = 0; a < 3; ++a) p[a] = fminf(fmaxf(r.o[a] + t * r.d[a], 0.0f), 1.0f);
 }
 
 __device__ inline bool inside(const float p[3], const float lo[3], const float hi[3]) {
@@ -286,14 +284,14 @@ __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, V
   int32_t e = -1;
   const float step_scale = 1.0f / (float)(1 << P);
   float dsf = 0.0f;
-  if (MODE == LR_STEP_FIXED) dsf = __fdiv_rn(__fsub_rn(r.t1, r.t0), (float)s.n_fixed);
+  if (MODE == LR_STEP_FIXED) dsf = (r.t1 - r.t0) / (float)s.n_fixed;
   float t = r.t0;
   int n = 0;
   for (;;) {
     float ts;
     if (MODE == LR_STEP_FIXED) {
       if (n >= s.n_fixed) break;
-      ts = __fadd_rn(r.t0, __fmul_rn((float)n + 0.5f, dsf));
+      ts = r.t0 + ((float)n + 0.5f) * dsf;
     } else {
       ts = t;
     }
@@ -305,8 +303,8 @@ __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, V
       const float2 b01 = b2[0], b23 = b2[1], b45 = b2[2];
       lo[0] = b01.x; lo[1] = b01.y; lo[2] = b23.x;
       hi[0] = b23.y; hi[1] = b45.x; hi[2] = b45.y;
-      const float side = fminf(fminf(__fsub_rn(hi[0], lo[0]), __fsub_rn(hi[1], lo[1])), __fsub_rn(hi[2], lo[2]));
-      ds_e = __fmul_rn(side, step_scale);
+      const float side = fminf(fminf(hi[0] - lo[0], hi[1] - lo[1]), hi[2] - lo[2]);
+      ds_e = side * step_scale;
       for (int a = 0; a < 3; ++a) inv[a] = 1.0f / (hi[a] - lo[a]);
       Coef<NCF, CT>::load(s.bez, s.stride, e, c);
     }
@@ -319,7 +317,7 @@ __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, V
       sm.ds = dsf;
     } else {
       ds = ds_e;
-      sm.ds = fminf(ds_e, __fsub_rn(r.t1, ts));
+      sm.ds = fminf(ds_e, r.t1 - ts);
     }
     const float ux = fminf(fmaxf((p[0] - lo[0]) * inv[0], 0.0f), 1.0f);
     const float uy = fminf(fmaxf((p[1] - lo[1]) * inv[1], 0.0f), 1.0f);
@@ -347,7 +345,7 @@ __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, V
     const bool stop = vis.sample(s, sm);
     if (stop || n >= s.max_samples) break;
     if (MODE == LR_STEP_ADAPTIVE) {
-      t = __fadd_rn(ts, ds);
+      t = ts + ds;
       if (!(t < r.t1)) break;
     }
   }

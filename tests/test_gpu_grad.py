@@ -1,0 +1,147 @@
+"""GPU adjoint (lr_render_backward) against the oracle's reverse mode.
+
+The oracle differentiates its own FP64 Bezier-parameterised render (its own
+extraction); both sides receive the same dL/d(rgba) so the comparison isolates
+the adjoint.  Tolerance: 1e-4 of the largest gradient entry.
+"""
+import numpy as np
+import pytest
+import torch
+
+from conftest import workload
+from gpu_util import TOL_F32, oracle_parts, peak_rel, resized, say, scene
+
+pytestmark = pytest.mark.gpu
+
+_C = {}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _oracle_blocks(coef_key="A"):
+    from oracle import bezier as obez
+    from oracle.bspline import LREvaluator
+    if coef_key not in _C:
+        wl = workload("config5")
+        s = wl.spline if coef_key == "A" else wl.spline.with_coef(wl.extra["coef_target"])
+        ev = oracle_parts("config5")[0] if coef_key == "A" else LREvaluator(s)
+        _C[coef_key] = obez.extract(s, ev)
+    return _C[coef_key]
+
+
+def _oracle_grad(views, pix_per_view, g_per_view):
+    """Sum over views of the oracle's dL/dC and dL/dLUT for the given pixels and
+    upstream gradients."""
+    from oracle import grad as ograd
+    wl = workload("config5")
+    C = _oracle_blocks("A")
+    ei = oracle_parts("config5")[1]
+    gb = np.zeros_like(C)
+    gl = np.zeros((256, 4))
+    imgs = []
+    for v, (ii, jj), g in zip(views, pix_per_view, g_per_view):
+        rgba, ns, recs = ograd.forward_records(wl, v, C, ei, ii=ii, jj=jj)
+        imgs.append(rgba)
+        if g is None:
+            continue
+        b, l = ograd.backward(wl, C, recs, ii.size, g)
+        gb += b
+        gl += l
+    return gb, gl, imgs
+
+
+def _grid(v):
+    jj, ii = np.meshgrid(np.arange(v.height), np.arange(v.width), indexing="ij")
+    return ii.ravel(), jj.ravel()
+
+
+def test_backward_small_views():
+    import paper_1707_01170_amd as P
+    say("[gpu] backward small")
+    wl, sc = scene("config5")
+    views = [resized(v, w, h) for v, (w, h) in zip(wl.views, [(40, 28), (33, 17), (24, 40), (48, 48)])]
+    pix = [_grid(v) for v in views]
+    _, _, imgs = _oracle_grad(views, pix, [None] * 4)
+    rng = np.random.default_rng(3)
+    gs = [rng.normal(size=img.shape) for img in imgs]
+    gb_o, gl_o, _ = _oracle_grad(views, pix, gs)
+    rgba, offs, _ = P.render(sc, views)
+    g = torch.from_numpy(np.concatenate(gs).astype(np.float32)).cuda()
+    gb, gl = P.render_backward(sc, views, rgba, g)
+    torch.cuda.synchronize()
+    gb = gb.cpu().numpy()[:, :27]
+    e_b, r_b = peak_rel(gb, gb_o[:, 0, :])
+    e_l, r_l = peak_rel(gl.cpu().numpy(), gl_o)
+    say("backward small: dL/dC peak-rel %.3e rms %.3e | dL/dLUT %.3e rms %.3e" % (e_b, r_b, e_l, r_l))
+    assert e_b <= TOL_F32 and e_l <= TOL_F32
+
+
+def test_backward_full_size_sampled():
+    """Full 4 x 512^2 launch; the upstream gradient is non-zero on seeded
+    pixels only, which the oracle differentiates one by one."""
+    import paper_1707_01170_amd as P
+    say("[gpu] backward full")
+    wl, sc = scene("config5")
+    views = wl.views
+    rng = np.random.default_rng(9)
+    pix, gs_sparse = [], []
+    g = np.zeros((sum(v.width * v.height for v in views), 4), np.float32)
+    off = 0
+    for v in views:
+        ii = rng.integers(0, v.width, 128)
+        jj = rng.integers(0, v.height, 128)
+        key = jj * v.width + ii
+        key, first = np.unique(key, return_index=True)
+        ii, jj = ii[first], jj[first]
+        gv = rng.normal(size=(ii.size, 4))
+        g[off + key] = gv
+        pix.append((ii, jj))
+        gs_sparse.append(gv)
+        off += v.width * v.height
+    gb_o, gl_o, _ = _oracle_grad(views, pix, gs_sparse)
+    rgba, _, _ = P.render(sc, views)
+    gb, gl = P.render_backward(sc, views, rgba, torch.from_numpy(g).cuda())
+    torch.cuda.synchronize()
+    e_b, r_b = peak_rel(gb.cpu().numpy()[:, :27], gb_o[:, 0, :])
+    e_l, r_l = peak_rel(gl.cpu().numpy(), gl_o)
+    say("backward full-size sampled: dL/dC %.3e rms %.3e | dL/dLUT %.3e rms %.3e" % (e_b, r_b, e_l, r_l))
+    assert e_b <= TOL_F32 and e_l <= TOL_F32
+
+
+def test_autograd_l2_loss():
+    """RenderFunction end to end: L2 loss against target images rendered from
+    the second coefficient set, each side with its own images."""
+    import paper_1707_01170_amd as P
+    from oracle import grad as ograd
+    say("[gpu] autograd")
+    wl, sc = scene("config5")
+    views = [resized(v, 36, 28) for v in wl.views]
+    pix = [_grid(v) for v in views]
+    vol = sc.volume
+    bez_t, _ = vol.extract(wl.extra["coef_target"], "f32")
+    tgt, _, _ = P.render(sc, views, bezier=bez_t)
+    bez = vol.bezier.clone().requires_grad_(True)
+    lut = sc.lut.clone().requires_grad_(True)
+    out = P.RenderFunction.apply(bez, lut, sc, views)
+    loss = ((out[:, :3] - tgt[:, :3]) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    # oracle
+    from oracle import render as orr
+    Ct = _oracle_blocks("B")
+    ei = oracle_parts("config5")[1]
+    tg_o = [orr.render_view(wl, v, orr.BezierField(wl.spline, Ct), eidx=ei, ii=ii, jj=jj)[0]
+            for v, (ii, jj) in zip(views, pix)]
+    _, _, imgs = _oracle_grad(views, pix, [None] * 4)
+    gs = [ograd.l2_grad(a, b) for a, b in zip(imgs, tg_o)]
+    gb_o, gl_o, _ = _oracle_grad(views, pix, gs)
+    L_o = sum(ograd.l2_loss(a, b) for a, b in zip(imgs, tg_o))
+    assert abs(loss.item() - L_o) <= 1e-4 * L_o
+    e_b, _ = peak_rel(bez.grad.cpu().numpy()[:, :27], gb_o[:, 0, :])
+    e_l, _ = peak_rel(lut.grad.cpu().numpy(), gl_o)
+    say("autograd: loss %.6f vs %.6f; dL/dC %.3e dL/dLUT %.3e" % (loss.item(), L_o, e_b, e_l))
+    assert e_b <= 1e-3 and e_l <= 1e-3

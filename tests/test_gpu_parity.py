@@ -55,7 +55,7 @@ def test_extraction_f64_matches_oracle(which):
     from oracle.bspline import LREvaluator
     say("[gpu] extract", which)
     s = {"config1": lambda: workload("config1").spline,
-         "deg3": lambda: lrgen.small_random(p=(3, 3, 3), n=(3, 3, 3), n_ref=50, seed=32, dist="cluster"),
+         "deg3": lambda: lrgen.small_random(p=(3, 3, 3), n=(2, 2, 2), n_ref=50, seed=32, dist="cluster"),
          "vector": _small_vector}[which]()
     vol = P.Volume(s, blocks=4, dtype="f64")
     got = vol.bezier.cpu().numpy()
