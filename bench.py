@@ -120,6 +120,13 @@ def main():
     torch.cuda.synchronize()
     samples = int(ns.to(torch.int64).sum().item())
     log("samples per frame %d (%.1f per hit ray)" % (samples, samples / max(1, int((ns > 0).sum().item()))))
+    # lane efficiency of 8x8 tiles: samples / (64 * longest ray of the tile)
+    H, W = view.height, view.width
+    img = ns.view(H, W).to(torch.float32)
+    img = torch.nn.functional.pad(img, (0, (-W) % 8, 0, (-H) % 8))
+    tiles = img.view(img.shape[0] // 8, 8, img.shape[1] // 8, 8).permute(0, 2, 1, 3).reshape(-1, 64)
+    lane_eff = float(tiles.sum() / (64 * tiles.max(1).values.sum()))
+    log("tile lane efficiency %.3f" % lane_eff)
     out = torch.empty_like(rgba)
     stream = torch.cuda.current_stream(dev)
     for _ in range(args.warmup):
@@ -166,6 +173,7 @@ def main():
         "config": {"workload": "vector field (2,2,2) x3 comps, %d elements, 1920x1080 persp, adaptive step (Eq. 4)"
                                % vol.n_elem, "samples_per_frame": samples, "forest_blocks": args.blocks},
         "frames_per_s": fps,
+        "tile_lane_efficiency": lane_eff,
         "p50_ms": float(np.percentile(times, 50)),
         "p99_ms": float(np.percentile(times, 99)),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
