@@ -78,15 +78,39 @@ def _cpu_chunk(idx):
     return int(ns.sum())
 
 
+def serve_stream(n_req: int, dev):
+    """The request stream on the (3,3,3) blob volume with FP16 Bezier storage:
+    Poisson arrivals at 200/s, square views of 256..2048, continuous batching."""
+    import lrgen
+    import paper_1707_01170_amd as P
+    from paper_1707_01170_amd.serve import Server
+    wl = lrgen.cached("config2")
+    vol = P.Volume(wl.spline, blocks=128, dtype="f16", device=dev)
+    sc = P.Scene(vol, P.RenderParams.of(wl))
+    reqs = lrgen.config4_requests(n=n_req)
+    warm = Server(sc, budget_bytes=2 << 30).run(reqs[:8])
+    log("serving: warm-up %d requests" % warm.n)
+    st = Server(sc, budget_bytes=2 << 30, n_streams=3).run(reqs)
+    log("serving: %d requests, p50 %.1f ms p99 %.1f ms, offered %.3g px/s served %.3g px/s, %d launches"
+        % (st.n, st.p50_ms, st.p99_ms, st.offered_px_per_s, st.served_px_per_s, st.launches))
+    return {"workload": "blob volume (3,3,3) scalar, %d elements, FP16 blocks / FP32 arithmetic; %d requests, "
+                        "Poisson 200/s, square 256..2048" % (vol.n_elem, st.n),
+            "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_ms": st.mean_ms, "offered_px_per_s": st.offered_px_per_s,
+            "served_px_per_s": st.served_px_per_s, "wall_s": st.wall_s, "launches": st.launches,
+            "views_per_launch": st.mean_views_per_launch, "budget_bytes": 2 << 30}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--blocks", type=int, default=64)
+    ap.add_argument("--blocks", type=int, default=256)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16"])
     ap.add_argument("--cpu-rays", type=int, default=2048, help="rays of the oracle CPU baseline (0: skip)")
     ap.add_argument("--copy-calib", action="store_true", help="also run a plain copy of known size (counter scale)")
+    ap.add_argument("--serve", type=int, default=1000,
+                    help="requests of the serving stream on the blob volume with FP16 blocks (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only (--gpus 1); multi-GPU runs are not part of this build",
@@ -152,6 +176,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log("copy calibration: 3 copies of %d bytes" % n)
+    serving = None
+    if args.serve > 0:
+        serving = serve_stream(args.serve, dev)
     fps = args.steps / wall
     value = samples * args.steps / wall
     fl = flops_per_sample(vol.p[0], vol.ncomp) * samples
@@ -180,6 +207,7 @@ def main():
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
                      "flops_per_sample": flops_per_sample(vol.p[0], vol.ncomp), "kernel_ms": times.mean()},
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(res), flush=True)
 

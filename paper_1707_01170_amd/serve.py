@@ -1,0 +1,219 @@
+"""Continuous batching of camera views over a resident LR-spline volume.
+
+Requests (a camera view of any size, with an arrival time) are admitted as
+soon as output memory is free in a fixed arena (the memory budget), batched
+up to LR_MAX_VIEWS_PER_LAUNCH views per lr_render launch, and launched on
+whichever of a few streams has room, so a launch for new arrivals overlaps
+launches already on the device.  The volume (forest, element boxes, Bezier
+blocks) stays resident.  Completion is taken from device events; latency is
+completion minus arrival.  A request's image does not depend on what it was
+batched with (rays are independent), so results are identical alone and in
+the mix.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .api import Scene, render
+
+
+class Arena:
+    """First-fit allocator over a fixed RGBA pixel arena (the memory budget)."""
+
+    def __init__(self, pixels: int, device):
+        self.buf = torch.empty((pixels, 4), dtype=torch.float32, device=device)
+        self.free = [(0, pixels)]           # sorted (start, length)
+
+    @property
+    def capacity(self) -> int:
+        return self.buf.shape[0]
+
+    def alloc(self, n: int) -> Optional[int]:
+        for k, (s, ln) in enumerate(self.free):
+            if ln >= n:
+                if ln == n:
+                    self.free.pop(k)
+                else:
+                    self.free[k] = (s + n, ln - n)
+                return s
+        return None
+
+    def release(self, s: int, n: int):
+        self.free.append((s, n))
+        self.free.sort()
+        merged = []
+        for a, ln in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == a:
+                merged[-1] = (merged[-1][0], merged[-1][1] + ln)
+            else:
+                merged.append((a, ln))
+        self.free = merged
+
+
+@dataclass
+class Served:
+    index: int
+    arrival_s: float
+    pixels: int
+    admitted_s: float = -1.0
+    launched_s: float = -1.0
+    done_ms: float = -1.0              # device completion, ms after the start event
+    image: Optional[torch.Tensor] = None
+
+    @property
+    def latency_ms(self) -> float:
+        return self.done_ms - 1e3 * self.arrival_s
+
+
+@dataclass
+class ServeStats:
+    n: int
+    wall_s: float
+    p50_ms: float
+    p99_ms: float
+    mean_ms: float
+    max_ms: float
+    pixels: int
+    offered_px_per_s: float
+    served_px_per_s: float
+    launches: int
+    mean_views_per_launch: float
+    max_inflight: int
+    budget_pixels: int
+    results: List[Served] = field(default_factory=list, repr=False)
+
+
+class Server:
+    def __init__(self, scene: Scene, budget_bytes: int = 1 << 30, n_streams: int = 3,
+                 max_views: int = L.LR_MAX_VIEWS_PER_LAUNCH, max_pixels_per_launch: int = 1 << 24):
+        dev = scene.volume.device
+        self.scene = scene
+        self.arena = Arena(budget_bytes // 16, dev)
+        # streams at the default priority
+        self.streams = [torch.cuda.Stream(device=dev) for _ in range(n_streams)]
+        self.max_views = max_views
+        self.max_px = max_pixels_per_launch
+
+    def run(self, requests: Sequence, keep_images: bool = False, time_scale: float = 1.0) -> ServeStats:
+        """Serve requests (objects with .arrival_s and .view) in real time.
+        time_scale < 1 compresses the arrival times."""
+        order = sorted(range(len(requests)), key=lambda k: requests[k].arrival_s)
+        recs = [Served(k, requests[k].arrival_s * time_scale, requests[k].view.width * requests[k].view.height)
+                for k in range(len(requests))]
+        for r in recs:
+            if r.pixels > self.arena.capacity:
+                raise ValueError("request %d needs %d pixels, more than the budget %d"
+                                 % (r.index, r.pixels, self.arena.capacity))
+        pending = deque(order)
+        arrived = deque()
+        ready = deque()            # admitted: (index, offset)
+        inflight = []              # (event, stream_idx, [(index, offset)])
+        stream_busy = [0] * len(self.streams)
+        dev = self.scene.volume.device
+        start = torch.cuda.Event(enable_timing=True)
+        start.record(torch.cuda.current_stream(dev))
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        launches = views_launched = max_inflight = 0
+        done = 0
+        n = len(recs)
+        while done < n:
+            now = time.perf_counter() - t0
+            while pending and recs[pending[0]].arrival_s <= now:
+                arrived.append(pending.popleft())
+            while arrived:                                     # FIFO admission by memory
+                k = arrived[0]
+                off = self.arena.alloc(recs[k].pixels)
+                if off is None:
+                    break
+                arrived.popleft()
+                recs[k].admitted_s = now
+                ready.append((k, off))
+            progressed = False
+            while ready:
+                si = min(range(len(self.streams)), key=lambda i: stream_busy[i])
+                if stream_busy[si] >= 1:
+                    break
+                batch, px = [], 0
+                while ready and len(batch) < self.max_views and (not batch or px + recs[ready[0][0]].pixels <= self.max_px):
+                    k, off = ready.popleft()
+                    batch.append((k, off))
+                    px += recs[k].pixels
+                views = [requests[k].view for k, _ in batch]
+                with torch.cuda.stream(self.streams[si]):
+                    arr = _view_array_at(views, [off for _, off in batch])
+                    s = self.scene.struct()
+                    L.check(L.lib().lr_render(_byref(s), arr, len(views), _ptr(self.arena.buf), None,
+                                              _stream_handle(self.streams[si])))
+                    ev = torch.cuda.Event(enable_timing=True)
+                    ev.record(self.streams[si])
+                for k, _ in batch:
+                    recs[k].launched_s = now
+                inflight.append((ev, si, batch))
+                stream_busy[si] += 1
+                launches += 1
+                views_launched += len(batch)
+                progressed = True
+            max_inflight = max(max_inflight, len(inflight))
+            still = []
+            for ev, si, batch in inflight:
+                if ev.query():
+                    t_ms = start.elapsed_time(ev)
+                    for k, off in batch:
+                        recs[k].done_ms = t_ms
+                        if keep_images:
+                            recs[k].image = self.arena.buf[off:off + recs[k].pixels].clone()
+                        self.arena.release(off, recs[k].pixels)
+                        done += 1
+                    stream_busy[si] -= 1
+                    progressed = True
+                else:
+                    still.append((ev, si, batch))
+            inflight = still
+            if not progressed:
+                time.sleep(5e-5)
+        torch.cuda.synchronize(dev)
+        wall = time.perf_counter() - t0
+        lat = np.array([r.latency_ms for r in recs])
+        px = sum(r.pixels for r in recs)
+        span = max(r.arrival_s for r in recs) - min(r.arrival_s for r in recs)
+        return ServeStats(n=n, wall_s=wall, p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                          mean_ms=float(lat.mean()), max_ms=float(lat.max()), pixels=px,
+                          offered_px_per_s=px / span if span > 0 else float("inf"),
+                          served_px_per_s=px / wall, launches=launches,
+                          mean_views_per_launch=views_launched / max(1, launches), max_inflight=max_inflight,
+                          budget_pixels=self.arena.capacity, results=recs)
+
+
+def _view_array_at(views, offsets):
+    from .api import view_array
+    arr, _ = view_array(views, offsets)
+    return arr
+
+
+def _byref(s):
+    import ctypes
+    return ctypes.byref(s)
+
+
+def _ptr(t):
+    import ctypes
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(st):
+    import ctypes
+    return ctypes.c_void_p(st.cuda_stream)
+
+
+def render_alone(scene: Scene, view) -> torch.Tensor:
+    """The same request rendered by itself (for comparison)."""
+    out, _, _ = render(scene, [view])
+    return out

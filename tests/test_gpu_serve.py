@@ -1,0 +1,57 @@
+"""Serving: continuous batching of mixed-resolution views (GPU)."""
+import numpy as np
+import pytest
+import torch
+
+import lrgen
+from gpu_util import resized, say, scene
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+class Req:
+    def __init__(self, t, view):
+        self.arrival_s = t
+        self.view = view
+
+
+def _stream(n, seed, sizes=(40, 64, 96, 128, 200)):
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(0.002, n))
+    dirs = lrgen.random_directions(rng, n)
+    return [Req(float(t[k]), lrgen.sphere_view(dirs[k], int(rng.choice(sizes)), int(rng.choice(sizes))))
+            for k in range(n)]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_results_identical_alone_and_in_the_mix(dtype):
+    from paper_1707_01170_amd.serve import Server, render_alone
+    say("[gpu] serve mix", dtype)
+    _, sc = scene("config2", dtype=dtype)
+    reqs = _stream(60, 1)
+    srv = Server(sc, budget_bytes=16 * 200 * 200 * 6, n_streams=3)
+    st = srv.run(reqs, keep_images=True)
+    assert st.n == 60 and st.launches < 60 and st.max_inflight >= 1
+    for r in st.results:
+        alone = render_alone(sc, reqs[r.index].view)
+        assert torch.equal(r.image, alone), r.index
+        assert r.latency_ms > 0
+    say("serve mix %s: p50 %.2f ms p99 %.2f ms, %d launches, %.1f views/launch, max in flight %d"
+        % (dtype, st.p50_ms, st.p99_ms, st.launches, st.mean_views_per_launch, st.max_inflight))
+
+
+def test_tight_budget_queues_instead_of_failing():
+    from paper_1707_01170_amd.serve import Server
+    _, sc = scene("config5")
+    reqs = _stream(30, 2, sizes=(128, 200))
+    srv = Server(sc, budget_bytes=16 * 200 * 200 + 16, n_streams=2)   # one large request at a time
+    st = srv.run(reqs)
+    assert st.n == 30 and st.mean_views_per_launch <= 2.0
+    with pytest.raises(ValueError):
+        Server(sc, budget_bytes=16 * 64 * 64).run([Req(0.0, lrgen.sphere_view([1, 0, 0], 128, 128))])
