@@ -78,6 +78,52 @@ def _cpu_chunk(idx):
     return int(ns.sum())
 
 
+def adjoint_step(dev, steps: int = 10):
+    """One differentiable render step on the (2,2,2) scalar volume: forward of
+    4 views of 512^2, L2 loss against targets from the second coefficient set,
+    backward to the Bezier blocks and the table."""
+    import torch
+
+    import lrgen
+    import paper_1707_01170_amd as P
+    wl = lrgen.cached("config5")
+    vol = P.Volume(wl.spline, blocks=128, device=dev)
+    sc = P.Scene(vol, P.RenderParams.of(wl))
+    tgt_bez, _ = vol.extract(wl.extra["coef_target"], "f32")
+    tgt, _, _ = P.render(sc, wl.views, bezier=tgt_bez)
+    rgba, _, ns = P.render(sc, wl.views, nsamples=True)
+    samples = int(ns.to(torch.int64).sum())
+    bez = vol.bezier.clone().requires_grad_(True)
+    lut = sc.lut.clone().requires_grad_(True)
+
+    def step():
+        out = P.RenderFunction.apply(bez, lut, sc, wl.views)
+        loss = ((out[:, :3] - tgt[:, :3]) ** 2).sum()
+        loss.backward()
+        return loss
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fa, fb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        step()
+    b.record()
+    fa.record()
+    for _ in range(steps):
+        P.render(sc, wl.views, bezier=bez.detach())
+    fb.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    fms = fa.elapsed_time(fb) / steps
+    log("adjoint: forward+loss+backward %.3f ms (forward alone %.3f ms), %d samples per forward" % (ms, fms, samples))
+    return {"workload": "scalar (2,2,2), %d elements, 4 x 512^2 views, L2 loss, grad wrt Bezier blocks and table"
+                        % vol.n_elem, "step_ms": ms, "forward_ms": fms, "samples_per_forward": samples,
+            "samples_per_s_fwd_bwd": samples / (ms / 1e3)}
+
+
 def serve_stream(n_req: int, dev):
     """The request stream on the (3,3,3) blob volume with FP16 Bezier storage:
     Poisson arrivals at 200/s, square views of 256..2048, continuous batching."""
@@ -109,6 +155,7 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16"])
     ap.add_argument("--cpu-rays", type=int, default=16384, help="rays of the oracle CPU baseline (0: skip)")
     ap.add_argument("--copy-calib", action="store_true", help="also run a plain copy of known size (counter scale)")
+    ap.add_argument("--no-adjoint", dest="adjoint", action="store_false", help="skip the adjoint step timing")
     ap.add_argument("--serve", type=int, default=1000,
                     help="requests of the serving stream on the blob volume with FP16 blocks (0: skip)")
     args = ap.parse_args()
@@ -176,6 +223,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log("copy calibration: 3 copies of %d bytes" % n)
+    adjoint = adjoint_step(dev) if args.adjoint else None
     serving = None
     if args.serve > 0:
         serving = serve_stream(args.serve, dev)
@@ -208,6 +256,7 @@ def main():
                      "flops_per_sample": flops_per_sample(vol.p[0], vol.ncomp), "kernel_ms": times.mean()},
         "cpu_baseline": cpu,
         "serving": serving,
+        "adjoint": adjoint,
     }
     print(json.dumps(res), flush=True)
 

@@ -519,31 +519,73 @@ __global__ void lookup_kernel(const uint32_t* __restrict__ heads, const lr_kdnod
 // dL/da_i = g_C . (T_i C_src - (C_final - C_i)/(1 - a_i)) + g_alpha T_final/(1 - a_i);
 // da/dalpha = (ds/xi)(1 - a)/(1 - alpha) (0 if clamped); then through the table
 // interpolation (LUT rows i0, i1) and s = 255 (v - vmin)/(vmax - vmin) into the
-// Bezier coefficients of the sample's element (dv/dC_j = B_j(u)).  Gradients of
-// consecutive samples in one element are summed in registers and flushed
-// with atomics when the element changes; table gradients go to LDS first.
+// Bezier coefficients of the sample's element (dv/dC_j = B_j(u)).
+//
+// Accumulation: a lane sums the gradient of consecutive samples of one
+// element in registers; on element change it adds the sum into a workgroup
+// hash table in LDS (the rays of a 16x16 pixel group share most elements):
+// a slot is claimed for an element by compare-and-swap on its tag (linear
+// probing), values are added with LDS atomics, and the table is written to
+// global memory with atomics once, when the workgroup ends (if it fills, the
+// lane adds to global memory directly).  Table gradients are summed in
+// registers while the table row stays the same, then added into an LDS copy
+// of the table.
+template <int P>
+struct GradTable {
+  static constexpr int NB = (P + 1) * (P + 1) * (P + 1);
+  static constexpr int kSlots = P == 3 ? 128 : 256;   // per workgroup
+  static constexpr int kLog2Slots = P == 3 ? 7 : 8;
+  static constexpr int kProbes = 16;
+};
+
 template <int P>
 struct Adjoint : Composite {
-  static constexpr int NB = (P + 1) * (P + 1) * (P + 1);
+  static constexpr int NB = GradTable<P>::NB;
+  static constexpr int kSlots = GradTable<P>::kSlots;
   float Cfin[3];
   float Tfin;
   float gC[3];
   float gA;
   float* gbez;
   int64_t stride;
-  float* glut_s;          // LDS [256][4]
-  float range_scale;      // 255 / (vmax - vmin)
+  float* glut_s;              // LDS [256][4]
+  int32_t* htag;              // LDS [kSlots]: element id or -1
+  float* hval;                // LDS [kSlots][NB]
+  float range_scale;          // 255 / (vmax - vmin)
   const float4* lut;
   int32_t cur = -1;
   float acc[NB];
+  int32_t row = -1;           // table row i0 being accumulated
+  float g0[4], g1[4];         // sums for rows i0 and min(i0 + 1, 255)
 
-  __device__ inline void flush() {
-    if (cur >= 0) {
-      float* row = gbez + (int64_t)cur * stride;
-#pragma unroll
-      for (int j = 0; j < NB; ++j)
-        if (acc[j] != 0.0f) unsafeAtomicAdd(row + j, acc[j]);
+  __device__ inline void flush_row() {
+    if (row >= 0) {
+      const int r1 = row < 255 ? row + 1 : 255;
+      for (int ch = 0; ch < 4; ++ch) {
+        if (g0[ch] != 0.0f) atomicAdd(&glut_s[4 * row + ch], g0[ch]);
+        if (g1[ch] != 0.0f) atomicAdd(&glut_s[4 * r1 + ch], g1[ch]);
+      }
     }
+  }
+
+  __device__ inline void flush_elem() {
+    if (cur < 0) return;
+    uint32_t h = ((uint32_t)cur * 2654435761u) >> (32 - GradTable<P>::kLog2Slots);
+    for (int probe = 0; probe < GradTable<P>::kProbes; ++probe) {
+      const int32_t t = atomicCAS(&htag[h], -1, cur);
+      if (t == -1 || t == cur) {
+        float* v = hval + h * NB;
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+          if (acc[j] != 0.0f) atomicAdd(v + j, acc[j]);
+        return;
+      }
+      h = (h + 1) & (kSlots - 1);
+    }
+    float* out = gbez + (int64_t)cur * stride;
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+      if (acc[j] != 0.0f) unsafeAtomicAdd(out + j, acc[j]);
   }
 
   __device__ inline bool sample(const SceneK& s, const Sample<P>& sm) {
@@ -561,12 +603,15 @@ struct Adjoint : Composite {
     const float r = sm.ds * s.inv_xi;
     g_x[3] = sm.clamped ? 0.0f : g_a * r * om / (1.0f - sm.alpha);
     // table rows
+    if (sm.tf.i0 != row) {
+      flush_row();
+      row = sm.tf.i0;
+      for (int ch = 0; ch < 4; ++ch) g0[ch] = g1[ch] = 0.0f;
+    }
     const float w1 = sm.tf.w, w0 = 1.0f - sm.tf.w;
     for (int ch = 0; ch < 4; ++ch) {
-      if (g_x[ch] != 0.0f) {
-        atomicAdd(&glut_s[4 * sm.tf.i0 + ch], w0 * g_x[ch]);
-        atomicAdd(&glut_s[4 * sm.tf.i1 + ch], w1 * g_x[ch]);
-      }
+      g0[ch] = fmaf(w0, g_x[ch], g0[ch]);
+      g1[ch] = fmaf(w1, g_x[ch], g1[ch]);
     }
     const float4 l0 = lut[sm.tf.i0], l1 = lut[sm.tf.i1];
     float g_s = g_x[0] * (l1.x - l0.x);
@@ -575,7 +620,7 @@ struct Adjoint : Composite {
     g_s = fmaf(g_x[3], l1.w - l0.w, g_s);
     const float g_v = sm.tf.inside ? g_s * range_scale : 0.0f;
     if (sm.e != cur) {
-      flush();
+      flush_elem();
       cur = sm.e;
 #pragma unroll
       for (int j = 0; j < NB; ++j) acc[j] = 0.0f;
@@ -595,17 +640,25 @@ struct Adjoint : Composite {
     T = fmaf(-T, a, T);
     return T <= s.t_term;
   }
-  __device__ inline void finish(int) { flush(); }
+  __device__ inline void finish(int) {
+    flush_elem();
+    flush_row();
+  }
 };
 
 template <int P, int MODE>
 __global__ __launch_bounds__(kThreads) void backward_kernel(const SceneK s, const ViewsK vk, const float4* __restrict__ fwd,
                                                            const float4* __restrict__ grad, float* __restrict__ gbez,
                                                            float* __restrict__ glut) {
+  constexpr int NB = GradTable<P>::NB, S = GradTable<P>::kSlots;
   __shared__ float4 lut[256];
   __shared__ float glut_s[1024];
+  __shared__ int32_t htag[S];
+  __shared__ float hval[S * NB];
   lut[threadIdx.x] = s.lut[threadIdx.x];
   for (int i = threadIdx.x; i < 1024; i += kThreads) glut_s[i] = 0.0f;
+  for (int i = threadIdx.x; i < S; i += kThreads) htag[i] = -1;
+  for (int i = threadIdx.x; i < S * NB; i += kThreads) hval[i] = 0.0f;
   __syncthreads();
   const int64_t g = remap_xcd(blockIdx.x, gridDim.x);
   int v, px, py;
@@ -628,12 +681,19 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(const SceneK s, cons
       vis.gbez = gbez;
       vis.stride = s.stride;
       vis.glut_s = glut_s;
+      vis.htag = htag;
+      vis.hval = hval;
       vis.range_scale = 255.0f * s.inv_range;
       vis.lut = lut;
       march<P, 1, float, MODE, LR_COLOR_LUT>(s, r, lut, vis);
     }
   }
   __syncthreads();
+  // write the block's element sums and table gradient to global memory
+  for (int i = threadIdx.x; i < S * NB; i += kThreads) {
+    const int32_t t = htag[i / NB];
+    if (t >= 0 && hval[i] != 0.0f) unsafeAtomicAdd(gbez + (int64_t)t * s.stride + (i % NB), hval[i]);
+  }
   for (int i = threadIdx.x; i < 1024; i += kThreads)
     if (glut_s[i] != 0.0f) unsafeAtomicAdd(glut + i, glut_s[i]);
 }
