@@ -562,8 +562,8 @@ struct Adjoint : Composite {
     if (row >= 0) {
       const int r1 = row < 255 ? row + 1 : 255;
       for (int ch = 0; ch < 4; ++ch) {
-        if (g0[ch] != 0.0f) atomicAdd(&glut_s[4 * row + ch], g0[ch]);
-        if (g1[ch] != 0.0f) atomicAdd(&glut_s[4 * r1 + ch], g1[ch]);
+        atomicAdd(&glut_s[4 * row + ch], g0[ch]);
+        atomicAdd(&glut_s[4 * r1 + ch], g1[ch]);
       }
     }
   }
@@ -572,12 +572,12 @@ struct Adjoint : Composite {
     if (cur < 0) return;
     uint32_t h = ((uint32_t)cur * 2654435761u) >> (32 - GradTable<P>::kLog2Slots);
     for (int probe = 0; probe < GradTable<P>::kProbes; ++probe) {
-      const int32_t t = atomicCAS(&htag[h], -1, cur);
+      int32_t t = htag[h];                          // same-address reads broadcast
+      if (t == -1) t = atomicCAS(&htag[h], -1, cur);
       if (t == -1 || t == cur) {
         float* v = hval + h * NB;
 #pragma unroll
-        for (int j = 0; j < NB; ++j)
-          if (acc[j] != 0.0f) atomicAdd(v + j, acc[j]);
+        for (int j = 0; j < NB; ++j) atomicAdd(v + j, acc[j]);   // straight-line, no per-value branches
         return;
       }
       h = (h + 1) & (kSlots - 1);
