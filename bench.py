@@ -32,6 +32,22 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(blocks: int):
+    """HBM bytes per render launch from the committed counter summary, or None
+    if the render source changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "render_kernel_vector1080p_traffic.json")) as f:
+            rec = json.load(f)
+        with open(os.path.join(ROOT, "paper_1707_01170_amd", "csrc", "render.hip"), "rb") as f:
+            src = hashlib.sha1(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha1") != src or rec.get("forest_blocks") != blocks:
+        return None
+    return float(rec["traffic_bytes_per_launch"])
+
+
 def flops_per_sample(p: int, ncomp: int) -> int:
     """Algorithmic FP32 operations of one sample (transcendentals count 1):
     position 6, local coordinates 6, Bernstein bases 3*(5 | 10), tensor
@@ -232,6 +248,7 @@ def main():
     fl = flops_per_sample(vol.p[0], vol.ncomp) * samples
     kern_s = times.mean() / 1e3
     achieved = fl / kern_s / 1e12
+    traffic = measured_traffic(args.blocks)
     res = {
         "metric": "spline samples/s at 1080p (frames/s, p50/p99 frame latency alongside)",
         "value": value,
@@ -252,7 +269,8 @@ def main():
         "p50_ms": float(np.percentile(times, 50)),
         "p99_ms": float(np.percentile(times, 99)),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+                     "hbm_GBps": None if traffic is None else traffic / kern_s / 1e9,
                      "flops_per_sample": flops_per_sample(vol.p[0], vol.ncomp), "kernel_ms": times.mean()},
         "cpu_baseline": cpu,
         "serving": serving,
