@@ -153,3 +153,91 @@ def test_support_csr_matches_oracle():
         for e in range(0, s.n_elem, max(1, s.n_elem // 60)):
             assert np.array_equal(idx[ptr[e]:ptr[e + 1]], ev.bsplines_on_element(s.elem_box[e]))
         assert np.all(np.diff(ptr) >= np.prod([q + 1 for q in s.p]))
+
+
+def _scene_struct(**kw):
+    s = L.SceneC()
+    s.p[:] = kw.get("p", (2, 2, 2))
+    s.ncomp = kw.get("ncomp", 1)
+    s.n_elem = kw.get("n_elem", 10)
+    fake = 0x1000                      # never dereferenced: validation fails first
+    s.elem_box = s.bezier = s.heads = s.nodes = s.lut = fake
+    s.bezier_dtype = kw.get("dtype", L.LR_F32)
+    s.blocks[:] = kw.get("blocks", (4, 4, 4))
+    s.n_nodes = 1
+    s.vmin, s.vmax, s.xi = kw.get("vmin", 0.0), kw.get("vmax", 1.0), kw.get("xi", 1.0)
+    s.alpha_clamp, s.term_alpha = kw.get("alpha_clamp", 0.99), 0.99
+    s.step_mode = kw.get("step_mode", L.LR_STEP_ADAPTIVE)
+    s.n_fixed_steps = kw.get("n_fixed_steps", 0)
+    s.color_mode = kw.get("color_mode", L.LR_COLOR_LUT)
+    s.max_samples = kw.get("max_samples", 100)
+    return s
+
+
+@pytest.mark.parametrize("kw,status", [
+    ({"p": (2, 3, 2)}, L.LR_EINVAL),               # render kernels take equal degrees
+    ({"p": (4, 4, 4)}, L.LR_EINVAL),
+    ({"ncomp": 3}, L.LR_EINVAL),                   # 3 components need the hue colour mode
+    ({"dtype": L.LR_F64}, L.LR_EINVAL),
+    ({"blocks": (3, 4, 4)}, L.LR_ENOTPOW2),
+    ({"vmax": 0.0}, L.LR_EINVAL),
+    ({"xi": 0.0}, L.LR_EINVAL),
+    ({"alpha_clamp": 1.0}, L.LR_EINVAL),
+    ({"step_mode": L.LR_STEP_FIXED, "n_fixed_steps": 0}, L.LR_EINVAL),
+    ({"max_samples": 0}, L.LR_EINVAL),
+])
+def test_render_rejects_bad_scene(kw, status):
+    import lrgen
+    lib = L.lib()
+    s = _scene_struct(**kw)
+    arr, _ = P.api.view_array([lrgen.sphere_view([1, 0, 0], 8, 8)])
+    assert lib.lr_render(ctypes.byref(s), arr, 1, ctypes.c_void_p(0x1000), None, None) == status
+    assert lib.lr_last_error()
+
+
+def test_render_rejects_bad_views():
+    import lrgen
+    lib = L.lib()
+    s = _scene_struct()
+    v = lrgen.sphere_view([1, 0, 0], 8, 8)
+    arr, _ = P.api.view_array([v])
+    assert lib.lr_render(ctypes.byref(s), arr, 0, ctypes.c_void_p(0x1000), None, None) == L.LR_EINVAL
+    assert lib.lr_render(ctypes.byref(s), arr, 1, None, None, None) == L.LR_EINVAL
+    arr[0].width = 0
+    assert lib.lr_render(ctypes.byref(s), arr, 1, ctypes.c_void_p(0x1000), None, None) == L.LR_EINVAL
+    arr[0].width = 8
+    arr[0].proj = 7
+    assert lib.lr_render(ctypes.byref(s), arr, 1, ctypes.c_void_p(0x1000), None, None) == L.LR_EINVAL
+    arr[0].proj = L.LR_PERSP
+    arr[0].eye[0] = float("inf")
+    assert lib.lr_render(ctypes.byref(s), arr, 1, ctypes.c_void_p(0x1000), None, None) == L.LR_EINVAL
+
+
+def test_backward_rejects_vector_and_f16():
+    import lrgen
+    lib = L.lib()
+    arr, _ = P.api.view_array([lrgen.sphere_view([1, 0, 0], 8, 8)])
+    f = ctypes.c_void_p(0x1000)
+    s = _scene_struct(ncomp=3, color_mode=L.LR_COLOR_HUE)
+    assert lib.lr_render_backward(ctypes.byref(s), arr, 1, f, f, f, f, None) == L.LR_EINVAL
+    s = _scene_struct(dtype=L.LR_F16)
+    assert lib.lr_render_backward(ctypes.byref(s), arr, 1, f, f, f, f, None) == L.LR_EINVAL
+
+
+def test_lookup_and_extract_validate_first():
+    lib = L.lib()
+    f = ctypes.c_void_p(0x1000)
+    b = np.array([3, 4, 4], np.int32)
+    assert lib.lr_lookup(f, f, 1, b.ctypes.data, 10, f, 5, f, None) == L.LR_ENOTPOW2
+    b = np.array([4, 4, 4], np.int32)
+    assert lib.lr_lookup(f, f, 1, b.ctypes.data, 10, f, 0, f, None) == L.LR_OK       # empty batch
+    assert lib.lr_lookup(f, f, 1, b.ctypes.data, 0, f, 5, f, None) == L.LR_EINVAL
+    s = L.LRSplineDev()
+    s.p[:] = (2, 2, 2)
+    s.ncomp, s.kstride, s.n_bspl, s.n_elem = 1, 4, 10, 5
+    s.knots = s.coef = s.gamma = s.elem_box = s.csr_ptr = s.csr_idx = 0x1000
+    assert lib.lr_extract_bezier(ctypes.byref(s), 7, f, None, None) == L.LR_EINVAL
+    s.kstride = 3
+    assert lib.lr_extract_bezier(ctypes.byref(s), L.LR_F32, f, None, None) == L.LR_EINVAL
+    s.kstride, s.ncomp = 4, 5
+    assert lib.lr_extract_bezier(ctypes.byref(s), L.LR_F32, f, None, None) == L.LR_EINVAL

@@ -1,0 +1,131 @@
+"""The pins are sensitive: a plausible mistake planted in the oracle (on the
+CPU) makes the corresponding pin fail."""
+import numpy as np
+import pytest
+
+import oracle.bezier as obez
+import oracle.bspline as obs
+import oracle.camera as ocam
+import oracle.render as orr
+import test_oracle_pins as pins
+
+
+def _fails(fn, *a):
+    with pytest.raises(AssertionError):
+        fn(*a)
+
+
+def test_cox_de_boor_wrong_denominator(monkeypatch):
+    good = obs.cox_de_boor
+
+    def bad(x, t, p):                      # second weight uses t_{j+k} instead of t_{j+k+1}
+        x = np.asarray(x, dtype=np.float64)
+        t = np.asarray(t, dtype=np.float64)
+        m = x.shape[0]
+        N = np.zeros((m, p + 1))
+        for j in range(p + 1):
+            N[:, j] = (t[:, j] <= x) & (x < t[:, j + 1])
+        for k in range(1, p + 1):
+            Nn = np.zeros((m, p + 1 - k))
+            for j in range(p + 1 - k):
+                d1 = t[:, j + k] - t[:, j]
+                d2 = t[:, j + k] - t[:, j + 1]
+                w1 = np.divide(x - t[:, j], d1, out=np.zeros(m), where=d1 != 0)
+                w2 = np.divide(t[:, j + k + 1] - x, d2, out=np.zeros(m), where=d2 != 0)
+                Nn[:, j] = w1 * N[:, j] + w2 * N[:, j + 1]
+            N = Nn
+        return N[:, 0]
+
+    monkeypatch.setattr(obs, "cox_de_boor", bad)
+    _fails(pins.test_tensor_matches_scipy, (2, 2, 2), (4, 3, 5))
+    monkeypatch.setattr(obs, "cox_de_boor", good)
+    pins.test_tensor_matches_scipy((2, 2, 2), (4, 3, 5))
+
+
+def test_missing_gamma_weight(monkeypatch):
+    orig = obs.LREvaluator.partition_of_unity
+
+    def no_gamma(self, x):
+        x = np.asarray(x, dtype=np.float64).reshape(-1, 3)
+        pt, bs, val = self.basis(x)
+        return np.bincount(pt, weights=val, minlength=x.shape[0])
+
+    monkeypatch.setattr(obs.LREvaluator, "partition_of_unity", no_gamma)
+    _fails(pins.test_partition_of_unity, lambda: pins.lrgen.small_random(p=(2, 2, 2), n=(4, 4, 4), n_ref=40, seed=8))
+    monkeypatch.setattr(obs.LREvaluator, "partition_of_unity", orig)
+
+
+def test_compositing_without_transmittance(monkeypatch):
+    def bad(C, A, csrc, asrc, ds, xi):          # drops the (1 - alpha_dst) factor
+        T = (1.0 - asrc) ** (ds / xi)
+        C += (1.0 - T)[:, None] * csrc
+        A += (1.0 - T)
+        return T
+
+    monkeypatch.setattr(orr, "composite", bad)
+    _fails(pins.test_constant_field_closed_form, "adaptive")
+    _fails(pins.test_over_operator)
+
+
+def test_opacity_correction_exponent_inverted(monkeypatch):
+    def bad(C, A, csrc, asrc, ds, xi):          # xi / ds instead of ds / xi
+        T = (1.0 - asrc) ** (xi / ds)
+        C += ((1.0 - T) * (1.0 - A))[:, None] * csrc
+        A += (1.0 - T) * (1.0 - A)
+        return T
+
+    monkeypatch.setattr(orr, "composite", bad)
+    _fails(pins.test_constant_field_closed_form, "fixed")
+
+
+def test_bernstein_order_reversed(monkeypatch):
+    good = obez.bernstein
+
+    def bad(p, u):
+        return good(p, u)[..., ::-1]
+
+    monkeypatch.setattr(obez, "bernstein", bad)
+    _fails(pins.test_bernstein_basis)
+
+
+def test_extraction_axes_swapped(monkeypatch):
+    good = obez.extract
+
+    def bad(spline, ev, elems=None):
+        C = good(spline, ev, elems)
+        q = [v + 1 for v in spline.p]
+        return C.reshape(C.shape[0], C.shape[1], q[2], q[1], q[0]).transpose(0, 1, 4, 3, 2).reshape(C.shape)
+
+    monkeypatch.setattr(obez, "extract", bad)
+    _fails(pins.test_extraction_closed_form, (2, 2, 2), (3, 3, 3), 40, "uniform")
+
+
+def test_transfer_off_by_one(monkeypatch):
+    good = orr.transfer
+
+    def bad(v, lut, vmin, vmax):
+        rgba, st = good(np.asarray(v) + 1.0 / 255.0 * (vmax - vmin), lut, vmin, vmax)
+        return rgba, st
+
+    monkeypatch.setattr(orr, "transfer", bad)
+    _fails(pins.test_transfer_function)
+
+
+def test_camera_axes_swapped(monkeypatch):
+    good = ocam.primary_rays
+
+    def bad(view, ii, jj):
+        return good(view, jj % view.width, ii % view.height)
+
+    monkeypatch.setattr(ocam, "primary_rays", bad)
+    _fails(pins.test_perspective_rays_geometry)
+
+
+def test_hue_sign_flipped(monkeypatch):
+    good = orr.hue
+
+    def bad(fx, fy):
+        return good(fx, -fy)
+
+    monkeypatch.setattr(orr, "hue", bad)
+    _fails(pins.test_hsv_matches_colorsys)
