@@ -9,7 +9,8 @@ leg may import it; the product path never calls it and shares no code with it
 Modules
   bspline  Cox-de Boor evaluation of the LR B-splines (Eq. 1, Eq. 2)
   lookup   element search by linear scan (Sec. 3.2, the O(N) search)
-  bezier   Bezier blocks by interpolation (Sec. 3.2.3) and Bernstein evaluation
+  bezier   Bezier blocks by interpolation (Sec. 3.2.3), Bernstein evaluation, and
+           the adjoint of the (linear) change of basis
   camera   ray generation and sample positions replayed in IEEE FP32
   render   transfer function, sampling schedules (fixed, Eq. 4 adaptive, fine
            fixed) and front-to-back compositing (Alg. 2, Eq. 3)

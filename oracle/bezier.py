@@ -65,3 +65,33 @@ def evaluate(p, C: np.ndarray, box: np.ndarray, x: np.ndarray) -> np.ndarray:
     """Field value [m, ncomp] from Bezier blocks C [m, ncomp, nc] at x [m,3]."""
     B = basis_on_element(p, box, x)
     return np.einsum("mqj,mj->mq", C, B)
+
+
+def extract_adjoint(spline, evaluator, G: np.ndarray) -> np.ndarray:
+    """Adjoint of `extract` with respect to the LR coefficients: given
+    dL/dC [n_elem, ncomp, nc] returns dL/dc [n_bspl, ncomp] (FP64).
+
+    The change of basis of Sec. 3.2.3 is linear in the coefficients c_i of
+    Eq. 2: C_e = (M^-1 kron) F_e with F_e[k] = sum_i gamma_i c_i N_i(x_k) at
+    the element's collocation points x_k.  Its transpose takes G_e back
+    through the transposed inverse collocation matrices to point weights
+    H_e[k], then dL/dc_i = gamma_i sum_e sum_k N_i(x_k) H_e[k]."""
+    p = tuple(int(v) for v in spline.p)
+    box = spline.elem_box
+    n, nq = box.shape[0], spline.coef.shape[1]
+    nodes = [collocation_nodes(p[d]) for d in range(3)]
+    Minv = [np.linalg.inv(bernstein(p[d], nodes[d])) for d in range(3)]
+    H = np.asarray(G, dtype=np.float64).reshape(n, nq, p[2] + 1, p[1] + 1, p[0] + 1)
+    H = np.einsum("jk,nqzyj->nqzyk", Minv[0], H)
+    H = np.einsum("jk,nqzjx->nqzkx", Minv[1], H)
+    H = np.einsum("jk,nqjyx->nqkyx", Minv[2], H)
+    H = H.reshape(n, nq, -1).transpose(0, 2, 1).reshape(-1, nq)         # [(e, k), q]
+    uz, uy, ux = np.meshgrid(nodes[2], nodes[1], nodes[0], indexing="ij")
+    u = np.stack([ux.ravel(), uy.ravel(), uz.ravel()], axis=1)
+    lo, hi = box[:, None, :3], box[:, None, 3:]
+    x = (lo + u[None, :, :] * (hi - lo)).reshape(-1, 3)
+    pt, bs, val = evaluator.basis(x)
+    out = np.zeros((spline.coef.shape[0], nq))
+    for q in range(nq):
+        out[:, q] = np.bincount(bs, weights=val * H[pt, q], minlength=out.shape[0])
+    return out * spline.gamma[:, None]

@@ -129,3 +129,40 @@ def test_hue_sign_flipped(monkeypatch):
 
     monkeypatch.setattr(orr, "hue", bad)
     _fails(pins.test_hsv_matches_colorsys)
+
+
+def test_extraction_adjoint_untransposed(monkeypatch):
+    """The adjoint must apply the transposed inverse collocation matrices."""
+    def bad(spline, ev, G):
+        p = tuple(int(v) for v in spline.p)
+        n, nq = spline.elem_box.shape[0], spline.coef.shape[1]
+        nodes = [obez.collocation_nodes(p[d]) for d in range(3)]
+        Minv = [np.linalg.inv(obez.bernstein(p[d], nodes[d])) for d in range(3)]
+        H = np.asarray(G).reshape(n, nq, p[2] + 1, p[1] + 1, p[0] + 1)
+        H = np.einsum("kj,nqzyj->nqzyk", Minv[0], H)          # not transposed
+        H = np.einsum("kj,nqzjx->nqzkx", Minv[1], H)
+        H = np.einsum("kj,nqjyx->nqkyx", Minv[2], H)
+        H = H.reshape(n, nq, -1).transpose(0, 2, 1).reshape(-1, nq)
+        uz, uy, ux = np.meshgrid(nodes[2], nodes[1], nodes[0], indexing="ij")
+        u = np.stack([ux.ravel(), uy.ravel(), uz.ravel()], axis=1)
+        box = spline.elem_box
+        x = (box[:, None, :3] + u[None] * (box[:, None, 3:] - box[:, None, :3])).reshape(-1, 3)
+        pt, bs, val = ev.basis(x)
+        out = np.zeros((spline.coef.shape[0], nq))
+        for q in range(nq):
+            out[:, q] = np.bincount(bs, weights=val * H[pt, q], minlength=out.shape[0])
+        return out * spline.gamma[:, None]
+
+    monkeypatch.setattr(obez, "extract_adjoint", bad)
+    _fails(pins.test_extraction_adjoint_brute_force)
+    _fails(pins.test_extraction_adjoint_of_point_evaluation, lambda: pins.workload("config1").spline)
+
+
+def test_extraction_adjoint_without_gamma(monkeypatch):
+    good = obez.extract_adjoint
+
+    def bad(spline, ev, G):
+        return good(spline, ev, G) / spline.gamma[:, None]
+
+    monkeypatch.setattr(obez, "extract_adjoint", bad)
+    _fails(pins.test_extraction_adjoint_of_point_evaluation, lambda: pins.lrgen.small_random(p=(2, 2, 2), n=(3, 3, 3), n_ref=40, seed=11))

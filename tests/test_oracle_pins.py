@@ -371,3 +371,58 @@ def test_gradient_matches_finite_differences():
         for ch in (0, 3):
             fd = ograd.fd_lut(w, view, C, ei, ii, jj, target, int(row), ch, h=1e-3)
             assert abs(fd - gl[row, ch]) <= 1e-5 * max(1.0, abs(fd))
+
+
+# ---------------------------------------------------------------- adjoint of the change of basis
+def test_extraction_adjoint_brute_force():
+    """Transpose of the explicit extraction matrix, built column by column by
+    extracting unit coefficient vectors on a tiny mesh."""
+    s = lrgen.small_random(p=(2, 3, 1), n=(2, 2, 2), n_ref=6, seed=21)
+    nb = s.coef.shape[0]
+    cols = []
+    for i in range(nb):
+        c = np.zeros((nb, 1))
+        c[i, 0] = 1.0
+        si = s.with_coef(c)
+        cols.append(obez.extract(si, LREvaluator(si)).reshape(-1))
+    E = np.stack(cols, axis=1)                                   # [(e, q, j), i]
+    G = np.random.default_rng(5).normal(size=(s.n_elem, 1, E.shape[0] // s.n_elem))
+    ref = E.T @ G.reshape(-1)
+    got = obez.extract_adjoint(s, LREvaluator(s), G)[:, 0]
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("make", [
+    lambda: workload("config1").spline,
+    lambda: lrgen.small_random(p=(3, 3, 3), n=(3, 3, 3), n_ref=30, seed=9, ncomp=3),
+])
+def test_extraction_adjoint_of_point_evaluation(make):
+    """Closed form: the Bernstein basis of a point x inside element e, placed
+    at e, is the gradient of f(x) with respect to the Bezier block; its
+    adjoint image must be dL/dc_i = gamma_i N_i(x) (Eq. 2), each component."""
+    s = make()
+    ev = LREvaluator(s)
+    ei = ElementIndex(s.elem_box)
+    rng = np.random.default_rng(6)
+    x = rng.random((24, 3))
+    nq = s.coef.shape[1]
+    for xk in x:
+        e = int(ei.find(xk[None])[0])
+        B = obez.basis_on_element(s.p, s.elem_box[e:e + 1], xk[None])[0]
+        G = np.zeros((s.n_elem, nq, B.shape[0]))
+        G[e, :] = B * np.arange(1, nq + 1)[:, None]              # component q weighted by q+1
+        got = obez.extract_adjoint(s, ev, G)
+        pt, bs, val = ev.basis(xk[None])
+        ref = np.zeros((s.coef.shape[0], nq))
+        ref[bs] = (s.gamma[bs] * val)[:, None] * np.arange(1, nq + 1)
+        assert np.abs(got - ref).max() <= 1e-12 * nq
+
+
+def test_extraction_adjoint_dot_product():
+    """<E c, G> = <c, E^T G> for random c and G (vector field, degree 2)."""
+    s = lrgen.small_random(p=(2, 2, 2), n=(3, 3, 3), n_ref=40, seed=10, ncomp=3)
+    rng = np.random.default_rng(7)
+    G = rng.normal(size=(s.n_elem, 3, 27))
+    lhs = np.sum(obez.extract(s, LREvaluator(s)) * G)
+    rhs = np.sum(s.coef * obez.extract_adjoint(s, LREvaluator(s), G))
+    assert abs(lhs - rhs) <= 1e-12 * np.abs(G).sum()
