@@ -140,6 +140,58 @@ def adjoint_step(dev, steps: int = 10):
             "samples_per_s_fwd_bwd": samples / (ms / 1e3)}
 
 
+def lookup_sweep(dev, name: str, steps: int = 10):
+    """Frame time through each look-up structure of Sec. 3.2 on one workload:
+    k-d forests of 1 (a single k-d tree) to 512 blocks per axis (512 is the
+    O(1) table for knots at level <= 9) and the octree.  Images are identical
+    across structures; only the look-up cost differs."""
+    import torch
+
+    import lrgen
+    import paper_1707_01170_amd as P
+    wl = lrgen.cached(name)
+    prm = P.RenderParams.of(wl)
+    view = wl.views[0]
+    rows = []
+    ref = None
+    for kind, blocks in [("forest", 1), ("forest", 4), ("forest", 16), ("forest", 64), ("forest", 128),
+                         ("forest", 256), ("forest", 512), ("octree", 0)]:
+        t0 = time.perf_counter()
+        vol = P.Volume(wl.spline, blocks=max(blocks, 1), device=dev, lookup=kind)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        sc = P.Scene(vol, prm)
+        out, _, _ = P.render(sc, [view])
+        torch.cuda.synchronize()
+        same = None
+        if ref is None:
+            ref = out.clone()
+        else:
+            same = bool(torch.equal(out, ref))
+        for _ in range(2):
+            P.render(sc, [view], out=out)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            P.render(sc, [view], out=out)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        st = vol.look_stats
+        row = {"structure": kind if kind == "octree" else "forest %d^3" % blocks, "ms_per_frame": ms,
+               "build_s": build_s, "n_nodes": st["n_nodes"], "n_heads": st["n_heads"], "n_direct": st["n_direct"],
+               "depth_min": st["min_depth"], "depth_max": st["max_depth"], "depth_mean": st["mean_depth"],
+               "depth_var": st["var_depth"], "image_identical_to_first": same}
+        log("lookup sweep %s %-12s %8.3f ms  depth %d..%d mean %.3f var %.3f  nodes %d  direct %d/%d  build %.2f s"
+            % (name, row["structure"], ms, st["min_depth"], st["max_depth"], st["mean_depth"], st["var_depth"],
+               st["n_nodes"], st["n_direct"], st["n_heads"], build_s))
+        rows.append(row)
+        del vol, sc, out
+        torch.cuda.empty_cache()
+    return {"workload": "%s: %d elements, %dx%d view" % (name, wl.spline.n_elem, view.width, view.height),
+            "rows": rows}
+
+
 def serve_stream(n_req: int, dev):
     """The request stream on the (3,3,3) blob volume with FP16 Bezier storage:
     Poisson arrivals at 200/s, square views of 256..2048, continuous batching."""
@@ -172,6 +224,8 @@ def main():
     ap.add_argument("--cpu-rays", type=int, default=32768, help="rays of the oracle CPU baseline (0: skip)")
     ap.add_argument("--copy-calib", action="store_true", help="also run a plain copy of known size (counter scale)")
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false", help="skip the adjoint step timing")
+    ap.add_argument("--lookup-sweep", action="store_true",
+                    help="also time every look-up structure (forest sizes, octree) on the 1080p and blob workloads")
     ap.add_argument("--serve", type=int, default=1000,
                     help="requests of the serving stream on the blob volume with FP16 blocks (0: skip)")
     args = ap.parse_args()
@@ -240,6 +294,7 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 3 copies of %d bytes" % n)
     adjoint = adjoint_step(dev) if args.adjoint else None
+    sweep = [lookup_sweep(dev, n) for n in ("config3", "config2")] if args.lookup_sweep else None
     serving = None
     if args.serve > 0:
         serving = serve_stream(args.serve, dev)
@@ -276,6 +331,8 @@ def main():
         "serving": serving,
         "adjoint": adjoint,
     }
+    if sweep is not None:
+        res["lookup_sweep"] = sweep
     print(json.dumps(res), flush=True)
 
 

@@ -59,6 +59,10 @@ typedef int32_t lr_status;
 #define LR_PERSP 0
 #define LR_ORTHO 1
 
+#define LR_LOOKUP_FOREST 0  /* k-d forest (Sec. 3.2.1, Alg. 1); also the O(1) table when
+                               every block holds one element */
+#define LR_LOOKUP_OCTREE 1  /* element octree of a dyadic mesh (Sec. 3.2, Sec. 3.2.2) */
+
 #define LR_LEAF 0x80000000u /* head / child reference: element id in the low 31 bits */
 #define LR_MAX_VIEWS_PER_LAUNCH 16
 
@@ -126,6 +130,37 @@ lr_status lr_lookup(const uint32_t* heads, const lr_kdnode* nodes, int64_t n_nod
                     const int32_t blocks[3], int64_t n_elem, const float* points, int64_t n,
                     int32_t* elem_out, void* stream);
 
+/* --------------------------------------------------------------------- octree
+ * Sec. 3.2 lists an octree as the O(log N) look-up for meshes whose knots are
+ * dyadic; Sec. 3.2.2 stores it on the GPU as one buffer whose entries are
+ * either a node or, marked by the high bit, an element.  Here a cell met by
+ * one element (positive volume) is a leaf; any other cell is split into its
+ * eight children.  Device layout:
+ *   root   uint32: LR_LEAF | element (a one-element mesh) or node 0
+ *   nodes  uint32 [n_nodes][8]: child k (x bit 0, y bit 1, z bit 2 of k; bit
+ *          set = upper half) as a node index or LR_LEAF | element
+ * Descent for p in [0,1]^3: at level l (root l = 0) the child bit of axis a
+ * is min(floor(p_a 2^(l+1)), 2^(l+1) - 1) & 1.
+ * elem_box  host double [n_elem][6], every knot a multiple of 2^-24 (else
+ *           LR_EKNOT), tiling [0,1]^3 (gaps and overlaps: LR_EPARTITION).
+ * stats     optional: n_heads = 1, n_nodes, n_direct = 1 if the root is an
+ *           element; depth statistics over the leaves (depth = level). */
+typedef struct lr_octree_host lr_octree_host;   /* opaque host-side octree */
+
+lr_status lr_build_octree(const double* elem_box, int64_t n_elem, lr_octree_host** out,
+                          lr_forest_stats* stats);
+
+/* Copies a built octree into host buffers (root: one uint32; nodes:
+ * uint32 [n_nodes][8]); either pointer may be NULL to skip it. */
+lr_status lr_octree_export(const lr_octree_host* o, uint32_t* root, uint32_t* nodes);
+
+void lr_octree_free(lr_octree_host* o);
+
+/* Element ids of n points by the octree descent above (root, nodes on the
+ * device); points and elem_out as for lr_lookup. */
+lr_status lr_lookup_octree(const uint32_t* root, const uint32_t* nodes, int64_t n_nodes, int64_t n_elem,
+                           const float* points, int64_t n, int32_t* elem_out, void* stream);
+
 /* ------------------------------------------------------------- Bezier blocks
  * Sec. 3.2.3: on each element the LR-spline is one polynomial of tri-degree p;
  * it is rewritten in the tensor Bernstein basis of the element (a change of
@@ -175,6 +210,20 @@ typedef struct {
 lr_status lr_extract_bezier(const lr_lrspline* spl, int32_t out_dtype, void* bezier, double* range,
                             void* stream);
 
+/* Adjoint of lr_extract_bezier with respect to the LR coefficients c_i of
+ * Eq. 2.  The change of basis of Sec. 3.2.3 is linear in c, so for a gradient
+ * G_e = dL/dC_e of every Bezier block
+ *   dL/dc_i[q] += gamma_i sum_{e in supp N_i} sum_j G_e[q][j] bx_i[jx] by_i[jy] bz_i[jz]
+ * with the 1-D Bernstein vectors of the forward (FP64 throughout).
+ * grad_bezier: device, the block layout of grad_dtype (LR_F32 or LR_F64; rows
+ * of lr_bezier_stride(p, ncomp, grad_dtype)).  grad_coef: device double
+ * [n_bspl][ncomp], accumulated (+=) by FP64 atomic adds, so the order of the
+ * additions is unspecified (results agree to FP64 rounding); the caller
+ * zeroes it.  spl->coef is not read and may be NULL.  Elements whose gradient
+ * block is all zero are skipped. */
+lr_status lr_extract_bezier_backward(const lr_lrspline* spl, int32_t grad_dtype, const void* grad_bezier,
+                                     double* grad_coef, void* stream);
+
 /* ------------------------------------------------------------------- render */
 typedef struct {
     int32_t p[3];             /* tri-degree; the render kernels take p1 = p2 = p3 in 1..3 */
@@ -183,9 +232,9 @@ typedef struct {
     const float* elem_box;    /* device float [n_elem][6] */
     const void* bezier;       /* device [n_elem][stride] of bezier_dtype */
     int32_t bezier_dtype;     /* LR_F32 or LR_F16 (FP32 arithmetic either way) */
-    int32_t blocks[3];        /* forest blocks per axis */
-    const uint32_t* heads;    /* device, from lr_forest_export */
-    const lr_kdnode* nodes;   /* device */
+    int32_t blocks[3];        /* forest blocks per axis (LR_LOOKUP_FOREST) */
+    const uint32_t* heads;    /* device: forest heads, or the octree root */
+    const void* nodes;        /* device: lr_kdnode [n_nodes] (forest) or uint32 [n_nodes][8] (octree) */
     int64_t n_nodes;
     const float* lut;         /* device float [256][4] RGBA transfer function */
     float vmin, vmax;         /* value range mapped onto the table */
@@ -196,7 +245,7 @@ typedef struct {
     int32_t n_fixed_steps;    /* for LR_STEP_FIXED, >= 1 */
     int32_t color_mode;       /* LR_COLOR_LUT or LR_COLOR_HUE */
     int32_t max_samples;      /* per-ray sample cap, >= 1 */
-    int32_t pad;
+    int32_t lookup;           /* LR_LOOKUP_FOREST or LR_LOOKUP_OCTREE (heads, nodes, n_nodes) */
 } lr_scene;
 
 /* One camera (values in FP32).  Pixel (i, j), row 0 at the top, writes

@@ -1,8 +1,9 @@
 """MI355X-native direct volume rendering of LR-spline volumes.
 
 C ABI: include/lrvr.h; HIP kernels and host builders: csrc/; binding: _lib;
-Python API: api (Volume, Scene, render, RenderFunction, trace, lookup).
+Python API: api (Volume, Scene, render, RenderFunction, ExtractFunction, trace,
+lookup).
 """
-from .api import (Forest, RenderFunction, RenderParams, Scene, Volume, bezier_stride, lookup, render,  # noqa: F401
+from .api import (ExtractFunction, Forest, Octree, RenderFunction, RenderParams, Scene, Volume, bezier_stride, lookup, render,  # noqa: F401
                   render_backward, support_csr, trace, unpack)
 from ._build import build  # noqa: F401

@@ -11,6 +11,7 @@ LR_F32, LR_F16, LR_F64 = 0, 1, 2
 LR_STEP_FIXED, LR_STEP_ADAPTIVE = 0, 1
 LR_COLOR_LUT, LR_COLOR_HUE = 0, 1
 LR_PERSP, LR_ORTHO = 0, 1
+LR_LOOKUP_FOREST, LR_LOOKUP_OCTREE = 0, 1
 LR_LEAF = 0x80000000
 LR_MAX_VIEWS_PER_LAUNCH = 16
 
@@ -38,7 +39,7 @@ class SceneC(ctypes.Structure):
                 ("bezier_dtype", _c_i32), ("blocks", _c_i32 * 3), ("heads", _vp), ("nodes", _vp),
                 ("n_nodes", _c_i64), ("lut", _vp), ("vmin", _c_f32), ("vmax", _c_f32), ("xi", _c_f32),
                 ("alpha_clamp", _c_f32), ("term_alpha", _c_f32), ("step_mode", _c_i32),
-                ("n_fixed_steps", _c_i32), ("color_mode", _c_i32), ("max_samples", _c_i32), ("pad", _c_i32)]
+                ("n_fixed_steps", _c_i32), ("color_mode", _c_i32), ("max_samples", _c_i32), ("lookup", _c_i32)]
 
 
 class ViewC(ctypes.Structure):
@@ -58,10 +59,15 @@ SIGNATURES = {
     "lr_forest_export": (_c_i32, [_vp, _vp, _vp]),
     "lr_forest_free": (None, [_vp]),
     "lr_lookup": (_c_i32, [_vp, _vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _vp, _vp]),
+    "lr_build_octree": (_c_i32, [_vp, _c_i64, ctypes.POINTER(_vp), ctypes.POINTER(ForestStats)]),
+    "lr_octree_export": (_c_i32, [_vp, _vp, _vp]),
+    "lr_octree_free": (None, [_vp]),
+    "lr_lookup_octree": (_c_i32, [_vp, _vp, _c_i64, _c_i64, _vp, _c_i64, _vp, _vp]),
     "lr_bezier_stride": (_c_i64, [_vp, _c_i32, _c_i32]),
     "lr_build_support": (_c_i32, [_vp, _c_i64, _c_i32, _vp, _vp, _c_i64, _vp, _vp, _c_i64,
                                   ctypes.POINTER(_c_i64)]),
     "lr_extract_bezier": (_c_i32, [ctypes.POINTER(LRSplineDev), _c_i32, _vp, _vp, _vp]),
+    "lr_extract_bezier_backward": (_c_i32, [ctypes.POINTER(LRSplineDev), _c_i32, _vp, _vp, _vp]),
     "lr_render": (_c_i32, [ctypes.POINTER(SceneC), ctypes.POINTER(ViewC), _c_i32, _vp, _vp, _vp]),
     "lr_render_backward": (_c_i32, [ctypes.POINTER(SceneC), ctypes.POINTER(ViewC), _c_i32, _vp, _vp, _vp, _vp, _vp]),
     "lr_trace_rays": (_c_i32, [ctypes.POINTER(SceneC), ctypes.POINTER(ViewC), _vp, _c_i64, _c_i32, _vp, _vp, _vp,

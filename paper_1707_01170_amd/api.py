@@ -57,6 +57,30 @@ class Forest:
         return Forest(tuple(int(x) for x in b), heads, nodes, stats)
 
 
+@dataclass
+class Octree:
+    """Element octree of a dyadic mesh, built on the host (Sec. 3.2)."""
+    root: int
+    nodes: np.ndarray          # uint32 [n_nodes, 8]
+    stats: dict
+
+    @staticmethod
+    def build(elem_box: np.ndarray) -> "Octree":
+        lib = L.lib()
+        eb = np.ascontiguousarray(elem_box, dtype=np.float64)
+        h = ctypes.c_void_p()
+        st = L.ForestStats()
+        L.check(lib.lr_build_octree(_np_ptr(eb), eb.shape[0], ctypes.byref(h), ctypes.byref(st)))
+        try:
+            root = np.zeros(1, dtype=np.uint32)
+            nodes = np.empty((max(st.n_nodes, 0), 8), dtype=np.uint32)
+            L.check(lib.lr_octree_export(h, _np_ptr(root), _np_ptr(nodes) if st.n_nodes else None))
+        finally:
+            lib.lr_octree_free(h)
+        stats = {k: getattr(st, k) for k, _ in L.ForestStats._fields_}
+        return Octree(int(root[0]), nodes, stats)
+
+
 def support_csr(spline):
     """Element -> B-spline incidence (CSR, host C++)."""
     lib = L.lib()
@@ -83,22 +107,37 @@ _DT = {"f32": (L.LR_F32, torch.float32), "f16": (L.LR_F16, torch.float16), "f64"
 
 
 class Volume:
-    """An LR-spline volume resident on one GPU: element boxes, k-d forest and
-    Bezier blocks.  `spline` needs p, knots [n_bspl,3,k], gamma, coef
-    [n_bspl,ncomp] and elem_box [n_elem,6] (numpy, FP64)."""
+    """An LR-spline volume resident on one GPU: element boxes, look-up
+    structure (k-d forest, or an octree for dyadic meshes) and Bezier blocks.
+    `spline` needs p, knots [n_bspl,3,k], gamma, coef [n_bspl,ncomp] and
+    elem_box [n_elem,6] (numpy, FP64)."""
 
-    def __init__(self, spline, blocks=64, dtype="f32", device=None):
+    def __init__(self, spline, blocks=64, dtype="f32", device=None, lookup="forest"):
         self.device = torch.device(device if device is not None else "cuda")
         self.p = tuple(int(v) for v in spline.p)
         self.ncomp = int(spline.coef.shape[1])
         self.n_elem = int(spline.elem_box.shape[0])
         self.spline = spline
-        self.forest = Forest.build(spline.elem_box, blocks)
+        self.lookup = lookup
         dev = self.device
+        if lookup == "octree":
+            self.forest = None
+            self.octree = Octree.build(spline.elem_box)
+            self.look_stats = self.octree.stats
+            self.heads = torch.from_numpy(np.array([self.octree.root], np.uint32).view(np.int32)).to(dev)
+            nodes = self.octree.nodes if self.octree.nodes.shape[0] else np.zeros((1, 8), np.uint32)
+            self.n_nodes = int(self.octree.nodes.shape[0])
+        elif lookup == "forest":
+            self.octree = None
+            self.forest = Forest.build(spline.elem_box, blocks)
+            self.look_stats = self.forest.stats
+            self.heads = torch.from_numpy(self.forest.heads.view(np.int32)).to(dev)
+            nodes = self.forest.nodes if self.forest.nodes.shape[0] else np.zeros((1, 4), np.uint32)
+            self.n_nodes = int(self.forest.nodes.shape[0])
+        else:
+            raise ValueError("lookup must be 'forest' or 'octree'")
         self.elem_box = torch.from_numpy(np.ascontiguousarray(spline.elem_box, dtype=np.float32)).to(dev)
-        self.heads = torch.from_numpy(self.forest.heads.view(np.int32)).to(dev)
-        nodes = self.forest.nodes if self.forest.nodes.shape[0] else np.zeros((1, 4), np.uint32)
-        self.nodes = torch.from_numpy(nodes.view(np.int32)).to(dev)
+        self.nodes = torch.from_numpy(np.ascontiguousarray(nodes).view(np.int32)).to(dev)
         ptr, idx = support_csr(spline)
         self.csr_ptr = torch.from_numpy(ptr).to(dev)
         self.csr_idx = torch.from_numpy(idx).to(dev)
@@ -108,25 +147,61 @@ class Volume:
         self.bezier, self.bez_range = self.extract(spline.coef, dtype)
         self.bezier_dtype = dtype
 
-    def extract(self, coef, dtype="f32"):
-        """Bezier blocks of this mesh for a coefficient set [n_bspl, ncomp]
-        (FP64 change of basis on the GPU).  Returns (blocks, range[2])."""
-        code, tdt = _DT[dtype]
-        coef_t = torch.from_numpy(np.ascontiguousarray(coef, dtype=np.float64).reshape(self.knots.shape[0], -1)).to(self.device)
-        ncomp = coef_t.shape[1]
-        stride = bezier_stride(self.p, ncomp, code)
-        out = torch.empty((self.n_elem, stride), dtype=tdt, device=self.device)
-        rng = torch.empty(2, dtype=torch.float64, device=self.device)
+    def _spline(self, coef_t, ncomp) -> L.LRSplineDev:
         s = L.LRSplineDev()
         s.p[:] = self.p
         s.ncomp = ncomp
         s.kstride = self.knots.shape[2]
         s.n_bspl = self.knots.shape[0]
         s.n_elem = self.n_elem
-        s.knots, s.coef, s.gamma = self.knots.data_ptr(), coef_t.data_ptr(), self.gamma.data_ptr()
+        s.knots, s.gamma = self.knots.data_ptr(), self.gamma.data_ptr()
+        s.coef = 0 if coef_t is None else coef_t.data_ptr()
         s.elem_box, s.csr_ptr, s.csr_idx = self.elem_box64.data_ptr(), self.csr_ptr.data_ptr(), self.csr_idx.data_ptr()
+        return s
+
+    def extract(self, coef, dtype="f32"):
+        """Bezier blocks of this mesh for a coefficient set [n_bspl, ncomp]
+        (numpy or a device tensor; FP64 change of basis on the GPU).
+        Returns (blocks, range[2])."""
+        code, tdt = _DT[dtype]
+        if isinstance(coef, torch.Tensor):
+            coef_t = coef.detach().to(self.device, torch.float64).reshape(self.knots.shape[0], -1).contiguous()
+        else:
+            coef_t = torch.from_numpy(np.ascontiguousarray(coef, dtype=np.float64).reshape(self.knots.shape[0], -1)).to(self.device)
+        ncomp = coef_t.shape[1]
+        stride = bezier_stride(self.p, ncomp, code)
+        out = torch.empty((self.n_elem, stride), dtype=tdt, device=self.device)
+        rng = torch.empty(2, dtype=torch.float64, device=self.device)
+        s = self._spline(coef_t, ncomp)
         L.check(L.lib().lr_extract_bezier(ctypes.byref(s), code, _ptr(out), _ptr(rng), _stream(self.device)))
         return out, rng
+
+    def extract_backward(self, grad_bezier: torch.Tensor) -> torch.Tensor:
+        """dL/dc [n_bspl, ncomp] (FP64) from dL/d(blocks) in the block layout
+        (float32 or float64; adjoint of the change of basis on the GPU)."""
+        code = {torch.float32: L.LR_F32, torch.float64: L.LR_F64}[grad_bezier.dtype]
+        g = grad_bezier.contiguous()
+        ncomp = self.ncomp
+        assert g.shape == (self.n_elem, bezier_stride(self.p, ncomp, code)), g.shape
+        out = torch.zeros((self.knots.shape[0], ncomp), dtype=torch.float64, device=self.device)
+        s = self._spline(None, ncomp)
+        L.check(L.lib().lr_extract_bezier_backward(ctypes.byref(s), code, _ptr(g), _ptr(out), _stream(self.device)))
+        return out
+
+
+class ExtractFunction(torch.autograd.Function):
+    """Differentiable change of basis: LR coefficients (FP64 [n_bspl, ncomp])
+    -> float32 Bezier blocks of `volume`'s mesh."""
+
+    @staticmethod
+    def forward(ctx, coef, volume):
+        out, _ = volume.extract(coef, "f32")
+        ctx.volume = volume
+        return out
+
+    @staticmethod
+    def backward(ctx, grad):
+        return ctx.volume.extract_backward(grad.float()).to(grad.device), None
 
 
 @dataclass
@@ -190,10 +265,11 @@ class Scene:
         s.elem_box = v.elem_box.data_ptr()
         s.bezier = bez.data_ptr()
         s.bezier_dtype = {torch.float32: L.LR_F32, torch.float16: L.LR_F16}[bez.dtype]
-        s.blocks[:] = v.forest.blocks
+        s.blocks[:] = v.forest.blocks if v.forest is not None else (1, 1, 1)
+        s.lookup = L.LR_LOOKUP_OCTREE if v.lookup == "octree" else L.LR_LOOKUP_FOREST
         s.heads = v.heads.data_ptr()
         s.nodes = v.nodes.data_ptr()
-        s.n_nodes = int(v.forest.nodes.shape[0])
+        s.n_nodes = v.n_nodes
         s.lut = lut.data_ptr()
         s.vmin, s.vmax, s.xi = pr.vmin, pr.vmax, pr.xi
         s.alpha_clamp, s.term_alpha = pr.alpha_clamp, pr.term_alpha
@@ -267,11 +343,15 @@ def trace(scene: Scene, view, pixels: np.ndarray, max_out: int = 4096, bezier=No
 
 
 def lookup(volume: Volume, points) -> torch.Tensor:
-    """Element ids of points [n, 3] (Alg. 1 on the GPU)."""
+    """Element ids of points [n, 3] (Alg. 1, or the octree descent, on the GPU)."""
     pts = torch.as_tensor(points, dtype=torch.float32).to(volume.device).contiguous()
     out = torch.empty(pts.shape[0], dtype=torch.int32, device=volume.device)
+    if volume.lookup == "octree":
+        L.check(L.lib().lr_lookup_octree(_ptr(volume.heads), _ptr(volume.nodes), volume.n_nodes, volume.n_elem,
+                                         _ptr(pts), pts.shape[0], _ptr(out), _stream(volume.device)))
+        return out
     b = np.asarray(volume.forest.blocks, dtype=np.int32)
-    L.check(L.lib().lr_lookup(_ptr(volume.heads), _ptr(volume.nodes), int(volume.forest.nodes.shape[0]), _np_ptr(b),
+    L.check(L.lib().lr_lookup(_ptr(volume.heads), _ptr(volume.nodes), volume.n_nodes, _np_ptr(b),
                               volume.n_elem, _ptr(pts), pts.shape[0], _ptr(out), _stream(volume.device)))
     return out
 

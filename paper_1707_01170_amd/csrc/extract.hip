@@ -37,6 +37,8 @@ struct ExtractArgs {
   const int32_t* csr_idx;
   void* out;
   unsigned long long* range;   // order-preserving keys while the kernels run
+  const void* grad;            // backward: dL/dC in the bezier layout of dtype
+  double* grad_coef;           // backward: dL/dc [n_bspl][ncomp], accumulated
 };
 
 // Order-preserving map of doubles to unsigned 64-bit keys (no NaNs).
@@ -194,6 +196,90 @@ __global__ __launch_bounds__(kLanes) void extract_kernel(ExtractArgs a) {
   }
 }
 
+// Adjoint of extract_kernel with respect to c: the same wavefront-per-element
+// split and the same 1-D Bernstein vectors; each lane contracts the element's
+// gradient block with its B-spline's tensor Bernstein coefficients and adds
+// gamma_i times the result to dL/dc_i.  Elements whose gradient block is zero
+// (no ray reached them) add nothing.
+__global__ __launch_bounds__(kLanes) void extract_backward_kernel(ExtractArgs a) {
+  __shared__ double sg[256];
+  const int64_t e = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int NC = a.nb * a.ncomp;
+  bool any = false;
+  for (int jj = lane; jj < NC; jj += kLanes) {
+    const int64_t off = e * a.stride + jj;
+    const double g = a.dtype == LR_F64 ? static_cast<const double*>(a.grad)[off]
+                                       : (double)static_cast<const float*>(a.grad)[off];
+    sg[jj] = g;
+    any |= g != 0.0;
+  }
+  if (!__syncthreads_or(any)) return;
+  const int64_t b0 = a.csr_ptr[e], b1 = a.csr_ptr[e + 1];
+  const double* eb = a.elem_box + 6 * e;
+  const int px = a.p[0] + 1, py = a.p[1] + 1, pz = a.p[2] + 1;
+  for (int64_t q = b0 + lane; q < b1; q += kLanes) {
+    const int32_t bi = a.csr_idx[q];
+    if (bi < 0 || bi >= a.n_bspl) continue;
+    double beta[3][4];
+    bool ok = true;
+    for (int d = 0; d < 3 && ok; ++d)
+      ok = bezier_1d(a.knots + ((int64_t)bi * 3 + d) * a.kstride, a.p[d], eb[d], eb[3 + d], beta[d]);
+    if (!ok) continue;
+    const double gw = a.gamma[bi];
+    for (int c = 0; c < a.ncomp; ++c) {
+      const double* g = sg + c * a.nb;
+      double s = 0.0;
+      for (int jz = 0; jz < pz; ++jz) {
+        double sy = 0.0;
+        for (int jy = 0; jy < py; ++jy) {
+          double sx = 0.0;
+          for (int jx = 0; jx < px; ++jx) sx += g[jx + px * (jy + py * jz)] * beta[0][jx];
+          sy += sx * beta[1][jy];
+        }
+        s += sy * beta[2][jz];
+      }
+      atomicAdd(a.grad_coef + (int64_t)bi * a.ncomp + c, gw * s);
+    }
+  }
+}
+
+// Checks shared by the forward and the adjoint; fills the kernel arguments.
+lr_status prepare(const char* who, const lr_lrspline* spl, bool need_coef, int32_t dtype, ExtractArgs* a) {
+  using lrvr::fail;
+  if (!spl->knots || (need_coef && !spl->coef) || !spl->gamma || !spl->elem_box || !spl->csr_ptr ||
+      !spl->csr_idx)
+    return fail(LR_EINVAL, "%s: null array in the spline", who);
+  if (spl->n_elem <= 0 || spl->n_bspl <= 0 || spl->n_elem >= (int64_t)1 << 31)
+    return fail(LR_EINVAL, "%s: n_elem / n_bspl out of range", who);
+  if (spl->ncomp < 1 || spl->ncomp > 4) return fail(LR_EINVAL, "%s: ncomp must be 1..4", who);
+  int pmax = 0;
+  int nb = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (spl->p[d] < 1 || spl->p[d] > 3) return fail(LR_EINVAL, "%s: degree out of [1,3]", who);
+    pmax = spl->p[d] > pmax ? spl->p[d] : pmax;
+    nb *= spl->p[d] + 1;
+  }
+  if (spl->kstride < pmax + 2) return fail(LR_EINVAL, "%s: kstride < max(p)+2", who);
+  if (nb * spl->ncomp > 256) return fail(LR_EINVAL, "%s: more than 256 coefficients per element", who);
+  std::memset(a, 0, sizeof *a);
+  for (int d = 0; d < 3; ++d) a->p[d] = spl->p[d];
+  a->ncomp = spl->ncomp;
+  a->kstride = spl->kstride;
+  a->nb = nb;
+  a->dtype = dtype;
+  a->stride = lr_bezier_stride(spl->p, spl->ncomp, dtype);
+  a->n_bspl = spl->n_bspl;
+  a->n_elem = spl->n_elem;
+  a->knots = spl->knots;
+  a->coef = spl->coef;
+  a->gamma = spl->gamma;
+  a->elem_box = spl->elem_box;
+  a->csr_ptr = spl->csr_ptr;
+  a->csr_idx = spl->csr_idx;
+  return LR_OK;
+}
+
 }  // namespace
 
 using lrvr::fail;
@@ -201,38 +287,11 @@ using lrvr::fail;
 LR_API lr_status lr_extract_bezier(const lr_lrspline* spl, int32_t out_dtype, void* bezier, double* range,
                                    void* stream) {
   if (!spl || !bezier) return fail(LR_EINVAL, "lr_extract_bezier: null pointer");
-  if (!spl->knots || !spl->coef || !spl->gamma || !spl->elem_box || !spl->csr_ptr || !spl->csr_idx)
-    return fail(LR_EINVAL, "lr_extract_bezier: null array in the spline");
-  if (spl->n_elem <= 0 || spl->n_bspl <= 0 || spl->n_elem >= (int64_t)1 << 31)
-    return fail(LR_EINVAL, "lr_extract_bezier: n_elem / n_bspl out of range");
-  if (spl->ncomp < 1 || spl->ncomp > 4) return fail(LR_EINVAL, "lr_extract_bezier: ncomp must be 1..4");
-  int pmax = 0;
-  int nb = 1;
-  for (int d = 0; d < 3; ++d) {
-    if (spl->p[d] < 1 || spl->p[d] > 3) return fail(LR_EINVAL, "lr_extract_bezier: degree out of [1,3]");
-    pmax = spl->p[d] > pmax ? spl->p[d] : pmax;
-    nb *= spl->p[d] + 1;
-  }
-  if (spl->kstride < pmax + 2) return fail(LR_EINVAL, "lr_extract_bezier: kstride < max(p)+2");
   if (out_dtype != LR_F32 && out_dtype != LR_F16 && out_dtype != LR_F64)
     return fail(LR_EINVAL, "lr_extract_bezier: out_dtype must be LR_F32, LR_F16 or LR_F64");
-  if (nb * spl->ncomp > 256) return fail(LR_EINVAL, "lr_extract_bezier: more than 256 coefficients per element");
   ExtractArgs a;
-  std::memset(&a, 0, sizeof a);
-  for (int d = 0; d < 3; ++d) a.p[d] = spl->p[d];
-  a.ncomp = spl->ncomp;
-  a.kstride = spl->kstride;
-  a.nb = nb;
-  a.dtype = out_dtype;
-  a.stride = lr_bezier_stride(spl->p, spl->ncomp, out_dtype);
-  a.n_bspl = spl->n_bspl;
-  a.n_elem = spl->n_elem;
-  a.knots = spl->knots;
-  a.coef = spl->coef;
-  a.gamma = spl->gamma;
-  a.elem_box = spl->elem_box;
-  a.csr_ptr = spl->csr_ptr;
-  a.csr_idx = spl->csr_idx;
+  const lr_status st0 = prepare("lr_extract_bezier", spl, true, out_dtype, &a);
+  if (st0 != LR_OK) return st0;
   a.out = bezier;
   a.range = reinterpret_cast<unsigned long long*>(range);
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -241,5 +300,22 @@ LR_API lr_status lr_extract_bezier(const lr_lrspline* spl, int32_t out_dtype, vo
   if (range) hipLaunchKernelGGL(range_final, dim3(1), dim3(1), 0, st, a.range);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return fail(LR_EHIP, "lr_extract_bezier: %s", hipGetErrorString(err));
+  return LR_OK;
+}
+
+LR_API lr_status lr_extract_bezier_backward(const lr_lrspline* spl, int32_t grad_dtype, const void* grad_bezier,
+                                            double* grad_coef, void* stream) {
+  if (!spl || !grad_bezier || !grad_coef) return fail(LR_EINVAL, "lr_extract_bezier_backward: null pointer");
+  if (grad_dtype != LR_F32 && grad_dtype != LR_F64)
+    return fail(LR_EINVAL, "lr_extract_bezier_backward: grad_dtype must be LR_F32 or LR_F64");
+  ExtractArgs a;
+  const lr_status st0 = prepare("lr_extract_bezier_backward", spl, false, grad_dtype, &a);
+  if (st0 != LR_OK) return st0;
+  a.grad = grad_bezier;
+  a.grad_coef = grad_coef;
+  hipLaunchKernelGGL(extract_backward_kernel, dim3((unsigned)spl->n_elem), dim3(kLanes), 0,
+                     static_cast<hipStream_t>(stream), a);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return fail(LR_EHIP, "lr_extract_bezier_backward: %s", hipGetErrorString(err));
   return LR_OK;
 }

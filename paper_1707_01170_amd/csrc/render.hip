@@ -33,7 +33,7 @@ struct SceneK {
   const float* box;
   const void* bez;
   const uint32_t* heads;
-  const lr_kdnode* nodes;
+  const void* nodes;        // lr_kdnode (forest) or uint32[8] (octree) records
   const float4* lut;
   int64_t n_elem;
   int64_t n_nodes;
@@ -42,6 +42,7 @@ struct SceneK {
   float fbx, fby, fbz;
   float vmin, inv_range, inv_xi, alpha_clamp, t_term;
   int32_t n_fixed, max_samples;
+  int32_t lookup;           // LR_LOOKUP_FOREST or LR_LOOKUP_OCTREE
 };
 
 struct ViewsK {
@@ -125,6 +126,36 @@ __device__ inline int32_t forest_lookup(const uint32_t* __restrict__ heads, cons
   }
   const int64_t e = (r & LR_LEAF) ? (int64_t)(r & ~LR_LEAF) : 0;
   return e < n_elem ? (int32_t)e : 0;
+}
+
+// Octree descent (dyadic meshes): one 4-byte child reference per level; the
+// child of a level-l cell is picked by bit l+1 of floor(p * 2^(l+1)) per axis
+// (exact in FP32: p is scaled by a power of two).
+__device__ inline int32_t octree_lookup(const uint32_t* __restrict__ root, const uint32_t* __restrict__ nodes,
+                                        int64_t n_nodes, int64_t n_elem, const float p[3]) {
+  uint32_t r = root[0];
+  float scale = 2.0f;
+  int lim = 1;
+  for (int level = 0; level < 24 && !(r & LR_LEAF); ++level) {
+    if ((int64_t)r >= n_nodes) break;
+    const int cx = min((int)(p[0] * scale), lim) & 1;
+    const int cy = min((int)(p[1] * scale), lim) & 1;
+    const int cz = min((int)(p[2] * scale), lim) & 1;
+    r = nodes[8 * (int64_t)r + (cx | (cy << 1) | (cz << 2))];
+    scale *= 2.0f;
+    lim = 2 * lim + 1;
+  }
+  const int64_t e = (r & LR_LEAF) ? (int64_t)(r & ~LR_LEAF) : 0;
+  return e < n_elem ? (int32_t)e : 0;
+}
+
+template <int LK>
+__device__ inline int32_t find_element(const SceneK& s, const float p[3]) {
+  if constexpr (LK == LR_LOOKUP_OCTREE)
+    return octree_lookup(s.heads, static_cast<const uint32_t*>(s.nodes), s.n_nodes, s.n_elem, p);
+  else
+    return forest_lookup(s.heads, static_cast<const lr_kdnode*>(s.nodes), s.n_nodes, s.n_elem, s.bx, s.by, s.bz,
+                         s.fbx, s.fby, s.fbz, p);
 }
 
 // ---------------------------------------------------------------- Bezier blocks
@@ -323,7 +354,7 @@ struct Sample {
   TF tf;
 };
 
-template <int P, int NCOMP, typename CT, int MODE, int COLOR, class Visitor>
+template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK = LR_LOOKUP_FOREST, class Visitor>
 __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, Visitor& vis) {
   constexpr int NB = (P + 1) * (P + 1) * (P + 1);
   constexpr int NCF = NCOMP * NB;
@@ -347,7 +378,7 @@ __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, V
     float p[3];
     position(r, ts, p);
     if (!inside(p, lo, hi)) {
-      e = forest_lookup(s.heads, s.nodes, s.n_nodes, s.n_elem, s.bx, s.by, s.bz, s.fbx, s.fby, s.fbz, p);
+      e = find_element<LK>(s, p);
       const float2* b2 = reinterpret_cast<const float2*>(s.box + 6 * (int64_t)e);
       const float2 b01 = b2[0], b23 = b2[1], b45 = b2[2];
       lo[0] = b01.x; lo[1] = b01.y; lo[2] = b23.x;
@@ -458,7 +489,7 @@ __device__ inline bool locate(const ViewsK& vk, int64_t g, int& v, int& px, int&
   return px < vk.v[v].width && py < vk.v[v].height;
 }
 
-template <int P, int NCOMP, typename CT, int MODE, int COLOR>
+template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK>
 __global__ __launch_bounds__(kThreads) void render_kernel(const SceneK s, const ViewsK vk, float4* __restrict__ rgba,
                                                          uint32_t* __restrict__ nsamples) {
   __shared__ float4 lut[256];
@@ -474,12 +505,12 @@ __global__ __launch_bounds__(kThreads) void render_kernel(const SceneK s, const 
     int n = 0;
     __device__ inline void finish(int k) { n = k; }
   } vis;
-  if (r.hit) march<P, NCOMP, CT, MODE, COLOR>(s, r, lut, vis);
+  if (r.hit) march<P, NCOMP, CT, MODE, COLOR, LK>(s, r, lut, vis);
   rgba[o] = make_float4(vis.C[0], vis.C[1], vis.C[2], 1.0f - vis.T);
   if (nsamples) nsamples[o] = (uint32_t)vis.n;
 }
 
-template <int P, int NCOMP, typename CT, int MODE, int COLOR>
+template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK>
 __global__ __launch_bounds__(64) void trace_kernel(const SceneK s, const lr_view view, const int32_t* __restrict__ pix,
                                                    int64_t n, int32_t max_out, float* t_out, int32_t* e_out,
                                                    float* ds_out, int32_t* count) {
@@ -497,7 +528,7 @@ __global__ __launch_bounds__(64) void trace_kernel(const SceneK s, const lr_view
   int taken = 0;
   if (i >= 0 && j >= 0 && i < view.width && j < view.height) {
     const Ray r = make_ray(view, i, j);
-    if (r.hit) march<P, NCOMP, CT, MODE, COLOR>(s, r, lut, vis);
+    if (r.hit) march<P, NCOMP, CT, MODE, COLOR, LK>(s, r, lut, vis);
     taken = vis.k;
   }
   count[k] = taken;
@@ -511,6 +542,16 @@ __global__ void lookup_kernel(const uint32_t* __restrict__ heads, const lr_kdnod
   float p[3];
   for (int a = 0; a < 3; ++a) p[a] = fminf(fmaxf(pts[3 * k + a], 0.0f), 1.0f);
   out[k] = forest_lookup(heads, nodes, n_nodes, n_elem, bx, by, bz, (float)bx, (float)by, (float)bz, p);
+}
+
+__global__ void lookup_octree_kernel(const uint32_t* __restrict__ root, const uint32_t* __restrict__ nodes,
+                                     int64_t n_nodes, int64_t n_elem, const float* __restrict__ pts, int64_t n,
+                                     int32_t* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  float p[3];
+  for (int a = 0; a < 3; ++a) p[a] = fminf(fmaxf(pts[3 * k + a], 0.0f), 1.0f);
+  out[k] = octree_lookup(root, nodes, n_nodes, n_elem, p);
 }
 
 // ---------------------------------------------------------------- adjoint
@@ -715,8 +756,12 @@ lr_status make_scene(const lr_scene* sc, SceneK& s, bool need_forest = true) {
   if (!sc->elem_box || !sc->bezier || !sc->lut || (need_forest && (!sc->heads || (!sc->nodes && sc->n_nodes > 0))))
     return fail(LR_EINVAL, "null device array in the scene");
   if (sc->n_elem <= 0 || sc->n_elem >= (int64_t)LR_LEAF || sc->n_nodes < 0) return fail(LR_EINVAL, "bad n_elem / n_nodes");
-  for (int d = 0; d < 3; ++d)
-    if (!lrvr::is_pow2(sc->blocks[d]) || sc->blocks[d] > 512) return fail(LR_ENOTPOW2, "blocks must be powers of two <= 512");
+  if (sc->lookup != LR_LOOKUP_FOREST && sc->lookup != LR_LOOKUP_OCTREE)
+    return fail(LR_EINVAL, "lookup must be LR_LOOKUP_FOREST or LR_LOOKUP_OCTREE");
+  if (sc->n_nodes >= (int64_t)LR_LEAF) return fail(LR_EINVAL, "too many look-up nodes");
+  if (sc->lookup == LR_LOOKUP_FOREST)
+    for (int d = 0; d < 3; ++d)
+      if (!lrvr::is_pow2(sc->blocks[d]) || sc->blocks[d] > 512) return fail(LR_ENOTPOW2, "blocks must be powers of two <= 512");
   if (!(sc->vmax > sc->vmin) || !(sc->xi > 0.0f) || !(sc->alpha_clamp < 1.0f) || !(sc->alpha_clamp >= 0.0f) ||
       !(sc->term_alpha > 0.0f && sc->term_alpha <= 1.0f))
     return fail(LR_EINVAL, "need vmax > vmin, xi > 0, 0 <= alpha_clamp < 1, 0 < term_alpha <= 1");
@@ -728,9 +773,11 @@ lr_status make_scene(const lr_scene* sc, SceneK& s, bool need_forest = true) {
   s.n_elem = sc->n_elem;
   s.n_nodes = sc->n_nodes;
   s.stride = lr_bezier_stride(sc->p, sc->ncomp, sc->bezier_dtype);
-  s.bx = sc->blocks[0];
-  s.by = sc->blocks[1];
-  s.bz = sc->blocks[2];
+  s.lookup = sc->lookup;
+  const bool oct = sc->lookup == LR_LOOKUP_OCTREE;
+  s.bx = oct ? 1 : sc->blocks[0];
+  s.by = oct ? 1 : sc->blocks[1];
+  s.bz = oct ? 1 : sc->blocks[2];
   s.fbx = (float)s.bx;
   s.fby = (float)s.by;
   s.fbz = (float)s.bz;
@@ -770,8 +817,12 @@ int64_t pack_views(const lr_view* views, int32_t n, ViewsK& vk) {
 
 template <int P, int NCOMP, typename CT, int MODE, int COLOR>
 void launch_render(const SceneK& s, const ViewsK& vk, int64_t nblk, float* rgba, uint32_t* ns, hipStream_t st) {
-  hipLaunchKernelGGL((render_kernel<P, NCOMP, CT, MODE, COLOR>), dim3((unsigned)nblk), dim3(kThreads), 0, st, s, vk,
-                     reinterpret_cast<float4*>(rgba), ns);
+  if (s.lookup == LR_LOOKUP_OCTREE)
+    hipLaunchKernelGGL((render_kernel<P, NCOMP, CT, MODE, COLOR, LR_LOOKUP_OCTREE>), dim3((unsigned)nblk),
+                       dim3(kThreads), 0, st, s, vk, reinterpret_cast<float4*>(rgba), ns);
+  else
+    hipLaunchKernelGGL((render_kernel<P, NCOMP, CT, MODE, COLOR, LR_LOOKUP_FOREST>), dim3((unsigned)nblk),
+                       dim3(kThreads), 0, st, s, vk, reinterpret_cast<float4*>(rgba), ns);
 }
 
 template <int P, int NCOMP, int COLOR>
@@ -797,8 +848,13 @@ void dispatch_render(const lr_scene* sc, const SceneK& s, const ViewsK& vk, int6
 template <int P, int NCOMP, typename CT, int MODE, int COLOR>
 void launch_trace(const SceneK& s, const lr_view& v, const int32_t* pix, int64_t n, int32_t m, float* t, int32_t* e,
                   float* ds, int32_t* cnt, hipStream_t st) {
-  hipLaunchKernelGGL((trace_kernel<P, NCOMP, CT, MODE, COLOR>), dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, s, v,
-                     pix, n, m, t, e, ds, cnt);
+  const dim3 grid((unsigned)((n + 63) / 64));
+  if (s.lookup == LR_LOOKUP_OCTREE)
+    hipLaunchKernelGGL((trace_kernel<P, NCOMP, CT, MODE, COLOR, LR_LOOKUP_OCTREE>), grid, dim3(64), 0, st, s, v, pix, n,
+                       m, t, e, ds, cnt);
+  else
+    hipLaunchKernelGGL((trace_kernel<P, NCOMP, CT, MODE, COLOR, LR_LOOKUP_FOREST>), grid, dim3(64), 0, st, s, v, pix, n,
+                       m, t, e, ds, cnt);
 }
 
 template <int P>
@@ -894,6 +950,7 @@ LR_API lr_status lr_render_backward(const lr_scene* sc, const lr_view* views, in
   if (st != LR_OK) return st;
   if (sc->ncomp != 1 || sc->color_mode != LR_COLOR_LUT || sc->bezier_dtype != LR_F32)
     return fail(LR_EINVAL, "lr_render_backward: scalar fields with FP32 blocks only");
+  if (sc->lookup != LR_LOOKUP_FOREST) return fail(LR_EINVAL, "lr_render_backward: forest look-up only");
   if (!views || n_views < 1 || !rgba_fwd || !grad_rgba || !grad_bezier || !grad_lut)
     return fail(LR_EINVAL, "lr_render_backward: null pointer or no views");
   for (int i = 0; i < n_views; ++i)
@@ -920,5 +977,21 @@ LR_API lr_status lr_render_backward(const lr_scene* sc, const lr_view* views, in
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return fail(LR_EHIP, "lr_render_backward: %s", hipGetErrorString(err));
   }
+  return LR_OK;
+}
+
+LR_API lr_status lr_lookup_octree(const uint32_t* root, const uint32_t* nodes, int64_t n_nodes, int64_t n_elem,
+                                  const float* points, int64_t n, int32_t* elem_out, void* stream) {
+  if (!root || !points || !elem_out || n < 0 || n_nodes < 0 || (n_nodes > 0 && !nodes))
+    return fail(LR_EINVAL, "lr_lookup_octree: null pointer or negative size");
+  if (n_elem <= 0 || n_elem >= (int64_t)LR_LEAF || n_nodes >= (int64_t)LR_LEAF)
+    return fail(LR_EINVAL, "lr_lookup_octree: bad n_elem / n_nodes");
+  if (n == 0) return LR_OK;
+  if (n > ((int64_t)1 << 40)) return fail(LR_EINVAL, "lr_lookup_octree: too many points");
+  const int64_t nblk = (n + 255) / 256;
+  hipLaunchKernelGGL(lookup_octree_kernel, dim3((unsigned)nblk), dim3(256), 0, static_cast<hipStream_t>(stream), root,
+                     nodes, n_nodes, n_elem, points, n, elem_out);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return fail(LR_EHIP, "lr_lookup_octree: %s", hipGetErrorString(err));
   return LR_OK;
 }

@@ -241,3 +241,91 @@ def test_lookup_and_extract_validate_first():
     assert lib.lr_extract_bezier(ctypes.byref(s), L.LR_F32, f, None, None) == L.LR_EINVAL
     s.kstride, s.ncomp = 4, 5
     assert lib.lr_extract_bezier(ctypes.byref(s), L.LR_F32, f, None, None) == L.LR_EINVAL
+    # adjoint of the extraction: same checks, plus its own dtype and pointers
+    s.ncomp = 1
+    assert lib.lr_extract_bezier_backward(ctypes.byref(s), L.LR_F16, f, f, None) == L.LR_EINVAL
+    assert lib.lr_extract_bezier_backward(ctypes.byref(s), L.LR_F32, None, f, None) == L.LR_EINVAL
+    assert lib.lr_extract_bezier_backward(ctypes.byref(s), L.LR_F32, f, None, None) == L.LR_EINVAL
+    s.p[:] = (2, 4, 2)
+    assert lib.lr_extract_bezier_backward(ctypes.byref(s), L.LR_F64, f, f, None) == L.LR_EINVAL
+    assert b"degree" in lib.lr_last_error()
+    s.p[:] = (2, 2, 2)
+    s.coef = 0                                   # the adjoint does not read coef
+    s.gamma = 0
+    assert lib.lr_extract_bezier_backward(ctypes.byref(s), L.LR_F64, f, f, None) == L.LR_EINVAL
+    assert b"null array" in lib.lr_last_error()
+
+
+# ---------------------------------------------------------------- octree
+def descend_octree(oc, p):
+    """The documented octree descent over the exported arrays (test side)."""
+    pf = p.astype(np.float32)
+    out = np.empty(p.shape[0], dtype=np.int64)
+    for k in range(p.shape[0]):
+        r, level = oc.root, 0
+        while not r & L.LR_LEAF:
+            scale = np.float32(2.0 ** (level + 1))
+            c = np.minimum((pf[k] * scale).astype(np.int64), 2 ** (level + 1) - 1) & 1
+            r = int(oc.nodes[r, c[0] | (c[1] << 1) | (c[2] << 2)])
+            level += 1
+        out[k] = r & ~L.LR_LEAF
+    return out
+
+
+def _leaf_depths(oc):
+    if oc.root & L.LR_LEAF:
+        return [0]
+    out, stack = [], [(oc.root, 0)]
+    while stack:
+        r, d = stack.pop()
+        for c in oc.nodes[r]:
+            c = int(c)
+            if c & L.LR_LEAF:
+                out.append(d + 1)
+            else:
+                stack.append((c, d + 1))
+    return out
+
+
+@pytest.mark.parametrize("make", [
+    lambda: lrgen.small_random(p=(2, 2, 2), n=(4, 4, 4), n_ref=80, seed=21, dist="cluster"),
+    lambda: workload("config1").spline,
+    lambda: lrgen.small_random(p=(3, 1, 2), n=(2, 4, 8), n_ref=60, seed=22),
+])
+def test_octree_descent_equals_scan(make):
+    s = make()
+    oc = P.Octree.build(s.elem_box)
+    x = _probe_points(s.elem_box, 2000, 2)
+    assert np.array_equal(descend_octree(oc, x), ElementIndex(s.elem_box).find(x))
+    d = np.array(_leaf_depths(oc))
+    st = oc.stats
+    assert st["n_heads"] == 1 and st["n_nodes"] == oc.nodes.shape[0]
+    assert st["min_depth"] == d.min() and st["max_depth"] == d.max()
+    assert abs(st["mean_depth"] - d.mean()) < 1e-12 and abs(st["var_depth"] - d.var()) < 1e-12
+
+
+def test_octree_shapes_and_errors():
+    t = P.Octree.build(lrgen.tensor_spline((2, 2, 2), (4, 4, 4)).elem_box)
+    assert t.stats["n_nodes"] == 9 and t.stats["min_depth"] == 2 and t.stats["max_depth"] == 2
+    one = P.Octree.build(np.array([[0, 0, 0, 1, 1, 1.0]]))
+    assert one.root == L.LR_LEAF and one.stats["n_nodes"] == 0 and one.stats["n_direct"] == 1
+    # an element with sides 1/2 x 1/8 x 1/8 spans 16 leaves
+    a = lrgen.tensor_spline((1, 1, 1), (2, 8, 8)).elem_box
+    oa = P.Octree.build(a)
+    assert len(_leaf_depths(oa)) == 8 ** 3 and oa.stats["max_depth"] == 3
+    lib = L.lib()
+
+    def status(box):
+        eb = np.ascontiguousarray(box, dtype=np.float64)
+        h = ctypes.c_void_p()
+        st = lib.lr_build_octree(eb.ctypes.data, eb.shape[0], ctypes.byref(h), None)
+        if st == 0:
+            lib.lr_octree_free(h)
+        return st
+    assert status(np.array([[0, 0, 0, 0.1, 1, 1.0], [0.1, 0, 0, 1, 1, 1.0]])) == L.LR_EKNOT
+    assert status(np.array([[0, 0, 0, 0.5, 1, 1.0]])) == L.LR_EPARTITION
+    assert status(np.array([[0, 0, 0, 0.75, 1, 1.0], [0.25, 0, 0, 1, 1, 1.0]])) == L.LR_EPARTITION
+    assert status(np.array([[0, 0, 0, 2.0, 1, 1.0]])) == L.LR_EPARTITION
+    f = ctypes.c_void_p(0x1000)
+    assert lib.lr_lookup_octree(f, f, 1, 0, f, 5, f, None) == L.LR_EINVAL
+    assert lib.lr_lookup_octree(f, f, 1, 10, f, 0, f, None) == L.LR_OK

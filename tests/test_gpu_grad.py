@@ -145,3 +145,70 @@ def test_autograd_l2_loss():
     e_l, _ = peak_rel(lut.grad.cpu().numpy(), gl_o)
     say("autograd: loss %.6f vs %.6f; dL/dC %.3e dL/dLUT %.3e" % (loss.item(), L_o, e_b, e_l))
     assert e_b <= 1e-3 and e_l <= 1e-3
+
+
+# ------------------------------------------------ adjoint of the change of basis
+@pytest.mark.parametrize("case", ["config5", "vector_deg3"])
+def test_extraction_adjoint(case):
+    """lr_extract_bezier_backward against the oracle's transpose of its own
+    interpolation extraction, for a random dL/dC (FP32 and FP64 inputs)."""
+    import lrgen
+    import paper_1707_01170_amd as P
+    from oracle import bezier as obez
+    from oracle.bspline import LREvaluator
+    say("[gpu] extraction adjoint %s" % case)
+    if case == "config5":
+        s = workload("config5").spline
+        ev = oracle_parts("config5")[0]
+        blocks = 64
+    else:
+        s = lrgen.small_random(p=(3, 3, 3), n=(4, 4, 4), n_ref=40, seed=31, ncomp=3)
+        ev = LREvaluator(s)
+        blocks = 8
+    vol = P.Volume(s, blocks=blocks, dtype="f32")
+    nq, nc = s.coef.shape[1], int(np.prod([v + 1 for v in s.p]))
+    rng = np.random.default_rng(12)
+    G = rng.normal(size=(s.n_elem, nq, nc)).astype(np.float32)
+    G[rng.random(s.n_elem) < 0.3] = 0.0                    # elements no ray reached
+    ref = obez.extract_adjoint(s, ev, G.astype(np.float64))
+    for dt, tdt in (("f32", torch.float32), ("f64", torch.float64)):
+        stride = P.bezier_stride(s.p, nq, {"f32": 0, "f64": 2}[dt])
+        g = torch.zeros((s.n_elem, stride), dtype=tdt)
+        g[:, :nq * nc] = torch.from_numpy(G.reshape(s.n_elem, -1)).to(tdt)
+        got = vol.extract_backward(g.cuda()).cpu().numpy()
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        say("extraction adjoint %s (%s grad): rel err %.3e" % (case, dt, err))
+        assert err <= 1e-12
+
+
+def test_autograd_to_lr_coefficients():
+    """coef -> ExtractFunction -> RenderFunction -> L2 loss: dL/dc against the
+    oracle's reverse mode through its own render and extraction adjoint."""
+    import paper_1707_01170_amd as P
+    from oracle import bezier as obez
+    from oracle import grad as ograd
+    from oracle import render as orr
+    say("[gpu] autograd to LR coefficients")
+    wl, sc = scene("config5")
+    views = [resized(v, 32, 24) for v in wl.views]
+    pix = [_grid(v) for v in views]
+    vol = sc.volume
+    bez_t, _ = vol.extract(wl.extra["coef_target"], "f32")
+    tgt, _, _ = P.render(sc, views, bezier=bez_t)
+    coef = torch.from_numpy(np.ascontiguousarray(wl.spline.coef, dtype=np.float64)).cuda().requires_grad_(True)
+    bez = P.ExtractFunction.apply(coef, vol)
+    out = P.RenderFunction.apply(bez, sc.lut, sc, views)
+    loss = ((out[:, :3] - tgt[:, :3]) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    Ct = _oracle_blocks("B")
+    ei = oracle_parts("config5")[1]
+    tg_o = [orr.render_view(wl, v, orr.BezierField(wl.spline, Ct), eidx=ei, ii=ii, jj=jj)[0]
+            for v, (ii, jj) in zip(views, pix)]
+    _, _, imgs = _oracle_grad(views, pix, [None] * 4)
+    gs = [ograd.l2_grad(a, b) for a, b in zip(imgs, tg_o)]
+    gb_o, _, _ = _oracle_grad(views, pix, gs)
+    gc_o = obez.extract_adjoint(wl.spline, oracle_parts("config5")[0], gb_o)
+    e_c, r_c = peak_rel(coef.grad.cpu().numpy(), gc_o)
+    say("autograd to c: dL/dc peak-rel %.3e rms %.3e" % (e_c, r_c))
+    assert e_c <= 1e-3
