@@ -41,6 +41,25 @@ def cox_de_boor(x: np.ndarray, t: np.ndarray, p: int) -> np.ndarray:
     return N[:, 0]
 
 
+def cox_de_boor_derivative(x: np.ndarray, t: np.ndarray, p: int) -> np.ndarray:
+    """d/dx of the B-spline with local knots t[m, 0..p+1] at x[m] (FP64):
+      B'(x) = p/(t_p - t_0) B[t_0..t_p](x) - p/(t_{p+1} - t_1) B[t_1..t_{p+1}](x)
+    (the two degree p-1 B-splines on the leading and trailing p+1 knots; 0/0 := 0),
+    one-sided from the right like the half-open evaluation."""
+    x = np.asarray(x, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    m = x.shape[0]
+    if p == 0:
+        return np.zeros(m)
+    d1 = t[:, p] - t[:, 0]
+    d2 = t[:, p + 1] - t[:, 1]
+    lo = cox_de_boor(x, t[:, :p + 1], p - 1)
+    hi = cox_de_boor(x, t[:, 1:], p - 1)
+    w1 = np.divide(p * lo, d1, out=np.zeros(m), where=d1 != 0)
+    w2 = np.divide(p * hi, d2, out=np.zeros(m), where=d2 != 0)
+    return w1 - w2
+
+
 def support_contains(lo: np.ndarray, hi: np.ndarray, x: np.ndarray) -> np.ndarray:
     """Half-open containment lo <= x < hi per axis, closed where hi == x == 1."""
     return np.all((lo <= x) & ((x < hi) | ((x == 1.0) & (hi == 1.0))), axis=-1)
@@ -122,6 +141,20 @@ class LREvaluator:
             for q in range(self.gc.shape[1]):
                 out[s0:s0 + chunk, q] = np.bincount(pt, weights=val * self.gc[bs, q],
                                                     minlength=xs.shape[0])
+        return out
+
+    def gradient(self, x: np.ndarray) -> np.ndarray:
+        """Spatial gradient of f (Eq. 2) in FP64, shape [m, ncomp, 3]: the sum
+        of gamma_i c_i times the product rule over the three univariate factors."""
+        x = np.asarray(x, dtype=np.float64).reshape(-1, 3)
+        pt, bs = self.pairs(x)
+        val = [cox_de_boor(x[pt, d], self.s.knots[bs, d, :self.p[d] + 2], self.p[d]) for d in range(3)]
+        der = [cox_de_boor_derivative(x[pt, d], self.s.knots[bs, d, :self.p[d] + 2], self.p[d]) for d in range(3)]
+        out = np.zeros((x.shape[0], self.gc.shape[1], 3))
+        for a in range(3):
+            w = der[a] * val[(a + 1) % 3] * val[(a + 2) % 3]
+            for q in range(self.gc.shape[1]):
+                out[:, q, a] = np.bincount(pt, weights=w * self.gc[bs, q], minlength=x.shape[0])
         return out
 
     def partition_of_unity(self, x: np.ndarray) -> np.ndarray:

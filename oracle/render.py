@@ -20,6 +20,13 @@ Sampling schedules
   'fine'     fixed fine step 2^-12 (midpoints, last segment clipped), all FP64:
              the reference for the discretisation error of the schedules above.
 
+Local illumination (Sec. 4.1, optional): C_src is multiplied by the diffuse
+intensity I = max(0.4, |l . n|), n the unit normal of the isosurface through
+the sample (the normalised gradient of the scalar field; for vector fields the
+gradient of |f|, which is parallel to sum_c f_c grad f_c); I = 0.4 where the
+gradient vanishes.  l is a fixed unit vector ('directional') or the unit
+vector from the sample back along the ray towards the eye ('headlight').
+
 Transfer function: value range [vmin, vmax] maps to s = clamp((v-vmin)/(vmax-vmin),
 0, 1) * 255; RGBA = (1-w) LUT[i0] + w LUT[i1], i0 = floor(s), i1 = min(i0+1, 255),
 w = s - i0; alpha_src <- min(alpha_src, 1 - 2^-16).  'hue' colour mode (vector
@@ -92,6 +99,18 @@ def source_terms(f: np.ndarray, sc):
     return csrc, np.minimum(a_raw, sc.alpha_clamp), a_raw, v, st
 
 
+def illumination(f: np.ndarray, grad: np.ndarray, ldir: np.ndarray) -> np.ndarray:
+    """I = max(0.4, |l . n|) for field values f [m, ncomp], gradients
+    grad [m, ncomp, 3] and unit light vectors ldir [m, 3]."""
+    if f.shape[1] == 1:
+        n = grad[:, 0, :]
+    else:
+        n = (f[:, :, None] * grad).sum(axis=1)
+    nn = np.sqrt((n * n).sum(axis=1))
+    cos = np.divide(np.abs((n * ldir).sum(axis=1)), nn, out=np.zeros(nn.shape), where=nn > 0)
+    return np.maximum(0.4, cos)
+
+
 def composite(C, A, csrc, asrc, ds, xi):
     """One step of Alg. 2 for a batch of rays, in place (FP64)."""
     T = (1.0 - asrc) ** (ds / xi)
@@ -111,12 +130,28 @@ class Scene:
     color_mode: str
     step_mode: str
     n_fixed_steps: int
+    shading: str = "none"          # 'none', 'directional' or 'headlight'
+    light: tuple = (0.0, 0.0, 1.0)
 
     @staticmethod
-    def of(wl):
+    def of(wl, shading="none", light=(0.0, 0.0, 1.0)):
         return Scene(tuple(int(v) for v in wl.spline.p), np.asarray(wl.lut, dtype=np.float64),
                      float(wl.vmin), float(wl.vmax), float(wl.xi), float(wl.alpha_clamp),
-                     wl.color_mode, wl.step_mode, int(wl.n_fixed_steps))
+                     wl.color_mode, wl.step_mode, int(wl.n_fixed_steps), shading, tuple(light))
+
+    def light_dirs(self, d: np.ndarray) -> np.ndarray:
+        """Unit light vectors [m, 3] for rays of direction d [m, 3]."""
+        if self.shading == "headlight":
+            d = -np.asarray(d, dtype=np.float64)
+            return d / np.sqrt((d * d).sum(axis=1))[:, None]
+        l = np.asarray(self.light, dtype=np.float64)
+        return np.broadcast_to(l / np.sqrt((l * l).sum()), (np.asarray(d).shape[0], 3))
+
+    def shaded(self, field, x, e, f, csrc, d):
+        """C_src times the local illumination (unchanged without shading)."""
+        if self.shading == "none":
+            return csrc
+        return csrc * illumination(f, field.grad(x, e), self.light_dirs(d))[:, None]
 
 
 class LRField:
@@ -127,6 +162,9 @@ class LRField:
 
     def __call__(self, x, e):
         return self.ev.evaluate(x)
+
+    def grad(self, x, e):
+        return self.ev.gradient(x)
 
 
 class BezierField:
@@ -163,7 +201,9 @@ def render_rays(sc: Scene, elem_box, eidx: ElementIndex, field, o, d, t0, t1, hi
             tm = 0.5 * (a + b)
             x = np.clip(o64[idx] + tm[:, None] * d64[idx], 0.0, 1.0)
             e = eidx.find(x)
-            csrc, asrc, _, _, _ = source_terms(field(x, e), sc)
+            f = field(x, e)
+            csrc, asrc, _, _, _ = source_terms(f, sc)
+            csrc = sc.shaded(field, x, e, f, csrc, d[idx])
             Cs, As = C[idx], A[idx]
             composite(Cs, As, csrc, asrc, b - a, sc.xi)
             C[idx], A[idx] = Cs, As
@@ -180,6 +220,7 @@ def render_rays(sc: Scene, elem_box, eidx: ElementIndex, field, o, d, t0, t1, hi
             e = eidx.find(x)
             f = field(x, e)
             csrc, asrc, a_raw, v, st = source_terms(f, sc)
+            csrc = sc.shaded(field, x, e, f, csrc, d[idx])
             Cs, As = C[idx], A[idx]
             Tbefore = 1.0 - As
             T = composite(Cs, As, csrc, asrc, dsf[idx].astype(np.float64), sc.xi)
@@ -205,6 +246,7 @@ def render_rays(sc: Scene, elem_box, eidx: ElementIndex, field, o, d, t0, t1, hi
         dse = np.minimum(ds, t1[idx] - ti)
         f = field(x, e)
         csrc, asrc, a_raw, v, st = source_terms(f, sc)
+        csrc = sc.shaded(field, x, e, f, csrc, d[idx])
         Cs, As = C[idx], A[idx]
         Tbefore = 1.0 - As
         T = composite(Cs, As, csrc, asrc, dse.astype(np.float64), sc.xi)
@@ -219,7 +261,8 @@ def render_rays(sc: Scene, elem_box, eidx: ElementIndex, field, o, d, t0, t1, hi
     return np.concatenate([C, A[:, None]], axis=1), ns, recs
 
 
-def render_view(wl, view, field, eidx=None, ii=None, jj=None, mode="S", record=False):
+def render_view(wl, view, field, eidx=None, ii=None, jj=None, mode="S", record=False, shading="none",
+                light=(0.0, 0.0, 1.0)):
     """Render pixels (ii, jj) of a view (all pixels by default)."""
     from .camera import pixel_grid
     if ii is None:
@@ -227,5 +270,5 @@ def render_view(wl, view, field, eidx=None, ii=None, jj=None, mode="S", record=F
     if eidx is None:
         eidx = ElementIndex(wl.spline.elem_box)
     o, d, t0, t1, hit = primary_rays(view, ii, jj)
-    return render_rays(Scene.of(wl), wl.spline.elem_box, eidx, field, o, d, t0, t1, hit,
+    return render_rays(Scene.of(wl, shading, light), wl.spline.elem_box, eidx, field, o, d, t0, t1, hit,
                        mode=mode, record=record)

@@ -166,3 +166,22 @@ def test_extraction_adjoint_without_gamma(monkeypatch):
 
     monkeypatch.setattr(obez, "extract_adjoint", bad)
     _fails(pins.test_extraction_adjoint_of_point_evaluation, lambda: pins.lrgen.small_random(p=(2, 2, 2), n=(3, 3, 3), n_ref=40, seed=11))
+
+
+def test_derivative_factor_wrong(monkeypatch):
+    good = obs.cox_de_boor_derivative
+
+    def bad(x, t, p):                      # factor p - 1 instead of p
+        return good(x, t, p) * (p - 1) / p
+
+    monkeypatch.setattr(obs, "cox_de_boor_derivative", bad)
+    _fails(pins.test_gradient_of_reproduced_polynomial, (2, 2, 2), (3, 3, 3), 40, "uniform")
+
+
+def test_illumination_unnormalised(monkeypatch):
+    def bad(f, grad, ldir):                 # forgets to normalise the gradient
+        n = grad[:, 0, :] if f.shape[1] == 1 else (f[:, :, None] * grad).sum(axis=1)
+        return np.maximum(0.4, np.abs((n * ldir).sum(axis=1)))
+
+    monkeypatch.setattr(orr, "illumination", bad)
+    _fails(pins.test_illumination_of_linear_field, "lut")

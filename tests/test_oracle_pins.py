@@ -426,3 +426,87 @@ def test_extraction_adjoint_dot_product():
     lhs = np.sum(obez.extract(s, LREvaluator(s)) * G)
     rhs = np.sum(s.coef * obez.extract_adjoint(s, LREvaluator(s), G))
     assert abs(lhs - rhs) <= 1e-12 * np.abs(G).sum()
+
+
+# ---------------------------------------------------------------- gradient and local illumination
+def _poly_grad(A, x):
+    g = np.zeros((x.shape[0], 3))
+    for a in range(A.shape[0]):
+        for b in range(A.shape[1]):
+            for c in range(A.shape[2]):
+                m = A[a, b, c]
+                if a:
+                    g[:, 0] += m * a * x[:, 0] ** (a - 1) * x[:, 1] ** b * x[:, 2] ** c
+                if b:
+                    g[:, 1] += m * b * x[:, 0] ** a * x[:, 1] ** (b - 1) * x[:, 2] ** c
+                if c:
+                    g[:, 2] += m * c * x[:, 0] ** a * x[:, 1] ** b * x[:, 2] ** (c - 1)
+    return g
+
+
+@pytest.mark.parametrize("p,n,n_ref,dist", [((2, 2, 2), (3, 3, 3), 40, "uniform"),
+                                            ((3, 1, 2), (2, 4, 3), 40, "cluster")])
+def test_gradient_of_reproduced_polynomial(p, n, n_ref, dist):
+    """A polynomial of tri-degree <= p kept through refinement: the LR gradient
+    is the polynomial's derivative (Eq. 2 differentiated term by term)."""
+    s, A = _poly_spline(p, n, n_ref, 17, dist)
+    x = np.random.default_rng(18).random((5000, 3))
+    g = LREvaluator(s).gradient(x)[:, 0, :]
+    ref = _poly_grad(A, x)
+    assert np.abs(g - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max())
+
+
+def test_gradient_matches_central_differences():
+    """Degree 2 with simple knots is C^1: central differences of the value."""
+    s = lrgen.small_random(p=(2, 2, 2), n=(4, 4, 4), n_ref=40, seed=19, ncomp=3)
+    ev = LREvaluator(s)
+    x = 0.05 + 0.9 * np.random.default_rng(20).random((2000, 3))
+    g = ev.gradient(x)
+    h = 1e-6
+    for a in range(3):
+        dx = np.zeros(3)
+        dx[a] = h
+        fd = (ev.evaluate(x + dx) - ev.evaluate(x - dx)) / (2 * h)
+        assert np.abs(fd - g[:, :, a]).max() <= 1e-6 * max(1.0, np.abs(g).max())
+
+
+@pytest.mark.parametrize("color", ["lut", "hue"])
+def test_illumination_of_linear_field(color):
+    """f linear (reproduced exactly at degree 2): the normal is constant, so a
+    directional light scales every C_src, hence C, by I = max(0.4, |l.a|/|a|)
+    and leaves alpha unchanged (Sec. 4.1); for a vector field (f, f, f) the
+    normal of |f| is the same."""
+    import copy
+    A = np.zeros((3, 3, 3))
+    A[0, 0, 0], A[1, 0, 0], A[0, 1, 0], A[0, 0, 1] = 0.2, 0.3, -0.2, 0.25
+    t0 = lrgen.tensor_spline((2, 2, 2), (3, 3, 3))
+    M = [_marsden(2, t0.knots[:, d, 1:3]) for d in range(3)]
+    r = lrgen.Refiner((2, 2, 2), (3, 3, 3))
+    r.set_initial_coef(np.einsum("abc,ia,ib,ic->i", A, M[0], M[1], M[2]))
+    r.refine(np.random.default_rng(24).random((20, 3)))
+    s = r.export()
+    if color == "hue":
+        s = s.with_coef(np.repeat(s.coef, 3, axis=1))
+    w = lrgen.Workload("lin", s, lrgen.default_lut(), -0.5, 1.2, "adaptive", 0, color,
+                       [lrgen.sphere_view([0.3, -0.8, 0.5], 12, 10)])
+    ev = LREvaluator(s)
+    light = (0.6, 0.0, 0.8)
+    a = np.array([0.3, -0.2, 0.25])
+    I = max(0.4, abs(np.dot(a, light)) / np.linalg.norm(a))
+    assert I > 0.4
+    plain, _, _ = orr.render_view(w, w.views[0], orr.LRField(ev))
+    lit, _, _ = orr.render_view(w, w.views[0], orr.LRField(ev), shading="directional", light=light)
+    assert np.abs(lit[:, 3] - plain[:, 3]).max() == 0.0
+    assert np.abs(lit[:, :3] - I * plain[:, :3]).max() <= 1e-12
+    assert plain[:, :3].max() > 0.05
+    w2 = copy.copy(w)
+    head, _, _ = orr.render_view(w2, w.views[0], orr.LRField(ev), shading="headlight")
+    assert np.all(head[:, :3] >= 0.4 * plain[:, :3] - 1e-12) and np.all(head[:, :3] <= plain[:, :3] + 1e-12)
+
+
+def test_illumination_floor_where_gradient_vanishes():
+    f = np.array([[0.3], [0.5]])
+    g = np.zeros((2, 1, 3))
+    g[1, 0] = [0.0, 3.0, 4.0]
+    ld = np.array([[0.0, 0.0, 1.0], [0.0, 0.0, -1.0]])
+    assert np.allclose(orr.illumination(f, g, ld), [0.4, 0.8], atol=0, rtol=1e-15)
