@@ -63,6 +63,14 @@ typedef int32_t lr_status;
                                every block holds one element */
 #define LR_LOOKUP_OCTREE 1  /* element octree of a dyadic mesh (Sec. 3.2, Sec. 3.2.2) */
 
+/* Gradient-based local illumination (Sec. 4.1): C_src is multiplied by
+ * I = max(0.4, |l . n|), n the unit gradient of the scalar field (of |f| for
+ * 3-vectors, i.e. sum_q f_q grad f_q normalised), evaluated from the same
+ * Bezier block as the value; I = 0.4 where the gradient is zero. */
+#define LR_SHADE_NONE 0
+#define LR_SHADE_DIRECTIONAL 1  /* l = light (normalised), the same for every sample */
+#define LR_SHADE_HEADLIGHT 2    /* l = the ray direction (light at the eye, far away) */
+
 #define LR_LEAF 0x80000000u /* head / child reference: element id in the low 31 bits */
 #define LR_MAX_VIEWS_PER_LAUNCH 16
 
@@ -246,6 +254,8 @@ typedef struct {
     int32_t color_mode;       /* LR_COLOR_LUT or LR_COLOR_HUE */
     int32_t max_samples;      /* per-ray sample cap, >= 1 */
     int32_t lookup;           /* LR_LOOKUP_FOREST or LR_LOOKUP_OCTREE (heads, nodes, n_nodes) */
+    int32_t shading;          /* LR_SHADE_NONE, _DIRECTIONAL or _HEADLIGHT (forest look-up only) */
+    float light[3];           /* direction towards the light for LR_SHADE_DIRECTIONAL (any length > 0) */
 } lr_scene;
 
 /* One camera (values in FP32).  Pixel (i, j), row 0 at the top, writes
@@ -275,7 +285,8 @@ typedef struct {
 lr_status lr_render(const lr_scene* sc, const lr_view* views, int32_t n_views, float* rgba,
                     uint32_t* nsamples, void* stream);
 
-/* Adjoint of lr_render for scalar fields (ncomp 1, LR_COLOR_LUT, F32 blocks).
+/* Adjoint of lr_render for scalar fields (ncomp 1, LR_COLOR_LUT, F32 blocks,
+ * forest look-up, no shading).
  * Re-marches each ray with the forward's schedule (no per-sample storage) and
  * uses the forward image to form the suffix sums.  Accumulates (+=) into
  * grad_bezier (device float, the bezier layout) and grad_lut (device float

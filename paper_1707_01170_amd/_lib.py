@@ -12,6 +12,7 @@ LR_STEP_FIXED, LR_STEP_ADAPTIVE = 0, 1
 LR_COLOR_LUT, LR_COLOR_HUE = 0, 1
 LR_PERSP, LR_ORTHO = 0, 1
 LR_LOOKUP_FOREST, LR_LOOKUP_OCTREE = 0, 1
+LR_SHADE_NONE, LR_SHADE_DIRECTIONAL, LR_SHADE_HEADLIGHT = 0, 1, 2
 LR_LEAF = 0x80000000
 LR_MAX_VIEWS_PER_LAUNCH = 16
 
@@ -39,7 +40,8 @@ class SceneC(ctypes.Structure):
                 ("bezier_dtype", _c_i32), ("blocks", _c_i32 * 3), ("heads", _vp), ("nodes", _vp),
                 ("n_nodes", _c_i64), ("lut", _vp), ("vmin", _c_f32), ("vmax", _c_f32), ("xi", _c_f32),
                 ("alpha_clamp", _c_f32), ("term_alpha", _c_f32), ("step_mode", _c_i32),
-                ("n_fixed_steps", _c_i32), ("color_mode", _c_i32), ("max_samples", _c_i32), ("lookup", _c_i32)]
+                ("n_fixed_steps", _c_i32), ("color_mode", _c_i32), ("max_samples", _c_i32), ("lookup", _c_i32),
+                ("shading", _c_i32), ("light", _c_f32 * 3)]
 
 
 class ViewC(ctypes.Structure):
@@ -48,7 +50,7 @@ class ViewC(ctypes.Structure):
                 ("up", _c_f32 * 3), ("tx", _c_f32), ("ty", _c_f32)]
 
 
-assert ctypes.sizeof(KdNode) == 16 and ctypes.sizeof(ViewC) == 80 and ctypes.sizeof(SceneC) == 128
+assert ctypes.sizeof(KdNode) == 16 and ctypes.sizeof(ViewC) == 80 and ctypes.sizeof(SceneC) == 144
 assert ctypes.sizeof(ForestStats) == 48 and ctypes.sizeof(LRSplineDev) == 88
 
 # name: (restype, argtypes)

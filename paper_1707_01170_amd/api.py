@@ -216,6 +216,8 @@ class RenderParams:
     alpha_clamp: float = 1.0 - 2.0 ** -16
     term_alpha: float = 1.0 - 2.0 ** -16
     max_samples: int = 1 << 16
+    shading: str = "none"             # 'none', 'directional' or 'headlight' (Sec. 4.1 illumination)
+    light: tuple = (0.0, 0.0, 1.0)    # towards the light, for 'directional'
 
     @staticmethod
     def of(wl) -> "RenderParams":
@@ -277,6 +279,9 @@ class Scene:
         s.n_fixed_steps = int(pr.n_fixed_steps)
         s.color_mode = L.LR_COLOR_HUE if pr.color_mode == "hue" else L.LR_COLOR_LUT
         s.max_samples = int(pr.max_samples)
+        s.shading = {"none": L.LR_SHADE_NONE, "directional": L.LR_SHADE_DIRECTIONAL,
+                     "headlight": L.LR_SHADE_HEADLIGHT}[pr.shading]
+        s.light[:] = [float(x) for x in pr.light]
         return s
 
 

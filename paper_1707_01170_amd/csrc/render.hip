@@ -43,6 +43,8 @@ struct SceneK {
   float vmin, inv_range, inv_xi, alpha_clamp, t_term;
   int32_t n_fixed, max_samples;
   int32_t lookup;           // LR_LOOKUP_FOREST or LR_LOOKUP_OCTREE
+  int32_t shading;          // LR_SHADE_*
+  float light[3];           // unit vector towards a directional light
 };
 
 struct ViewsK {
@@ -241,6 +243,77 @@ __device__ inline float contract(const float* c, const float* bx, const float* b
   return acc;
 }
 
+// Bernstein basis and its derivative: d/du B^P_j = P (B^{P-1}_{j-1} - B^{P-1}_j).
+template <int P>
+__device__ inline void bernstein_d(float u, float b[P + 1], float db[P + 1]) {
+  const float v = 1.0f - u;
+  if constexpr (P == 1) {
+    b[0] = v;
+    b[1] = u;
+    db[0] = -1.0f;
+    db[1] = 1.0f;
+  } else if constexpr (P == 2) {
+    b[0] = v * v;
+    b[1] = 2.0f * u * v;
+    b[2] = u * u;
+    db[0] = -2.0f * v;
+    db[1] = 2.0f * (v - u);
+    db[2] = 2.0f * u;
+  } else {
+    const float v2 = v * v, u2 = u * u, uv = u * v;
+    b[0] = v2 * v;
+    b[1] = 3.0f * u * v2;
+    b[2] = 3.0f * u2 * v;
+    b[3] = u2 * u;
+    db[0] = -3.0f * v2;
+    db[1] = 3.0f * (v2 - 2.0f * uv);
+    db[2] = 3.0f * (2.0f * uv - u2);
+    db[3] = 3.0f * u2;
+  }
+}
+
+// Value and local-coordinate gradient (d/du, d/dv, d/dw) of one component,
+// sharing the partial sums: out = {f, f_u, f_v, f_w}.
+template <int P>
+__device__ inline void contract_grad(const float* c, const float* bx, const float* by, const float* bz,
+                                     const float* dx, const float* dy, const float* dz, float out[4]) {
+  constexpr int Q = P + 1;
+  float f = 0.0f, fu = 0.0f, fv = 0.0f, fw = 0.0f;
+#pragma unroll
+  for (int kz = 0; kz < Q; ++kz) {
+    float ay = 0.0f, ayu = 0.0f, ayv = 0.0f;
+#pragma unroll
+    for (int jy = 0; jy < Q; ++jy) {
+      float ax = 0.0f, axu = 0.0f;
+#pragma unroll
+      for (int ix = 0; ix < Q; ++ix) {
+        const float cv = c[(kz * Q + jy) * Q + ix];
+        ax = fmaf(cv, bx[ix], ax);
+        axu = fmaf(cv, dx[ix], axu);
+      }
+      ay = fmaf(ax, by[jy], ay);
+      ayu = fmaf(axu, by[jy], ayu);
+      ayv = fmaf(ax, dy[jy], ayv);
+    }
+    f = fmaf(ay, bz[kz], f);
+    fu = fmaf(ayu, bz[kz], fu);
+    fv = fmaf(ayv, bz[kz], fv);
+    fw = fmaf(ay, dz[kz], fw);
+  }
+  out[0] = f;
+  out[1] = fu;
+  out[2] = fv;
+  out[3] = fw;
+}
+
+// Diffuse intensity max(0.4, |l . n|) with n = g / |g| (0.4 where g = 0).
+__device__ inline float diffuse(const float l[3], const float g[3]) {
+  const float nn = fmaf(g[0], g[0], fmaf(g[1], g[1], g[2] * g[2]));
+  if (!(nn > 0.0f)) return 0.4f;
+  const float dot = fabsf(fmaf(l[0], g[0], fmaf(l[1], g[1], l[2] * g[2])));
+  return fmaxf(0.4f, dot * __builtin_amdgcn_rsqf(nn));
+}
+
 // ---------------------------------------------------------------- transfer function
 struct TF {
   float4 rgba;
@@ -354,7 +427,7 @@ struct Sample {
   TF tf;
 };
 
-template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK = LR_LOOKUP_FOREST, class Visitor>
+template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK = LR_LOOKUP_FOREST, int SH = 0, class Visitor>
 __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, Visitor& vis) {
   constexpr int NB = (P + 1) * (P + 1) * (P + 1);
   constexpr int NCF = NCOMP * NB;
@@ -402,10 +475,44 @@ __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, V
     const float ux = fminf(fmaxf((p[0] - lo[0]) * inv[0], 0.0f), 1.0f);
     const float uy = fminf(fmaxf((p[1] - lo[1]) * inv[1], 0.0f), 1.0f);
     const float uz = fminf(fmaxf((p[2] - lo[2]) * inv[2], 0.0f), 1.0f);
-    bernstein<P>(ux, sm.bx);
-    bernstein<P>(uy, sm.by);
-    bernstein<P>(uz, sm.bz);
-    if constexpr (COLOR == LR_COLOR_HUE) {
+    if constexpr (SH) {
+      // Local illumination (Sec. 4.1): value and gradient from the same block;
+      // world gradient = local gradient / element side.
+      float dx[P + 1], dy[P + 1], dz[P + 1];
+      bernstein_d<P>(ux, sm.bx, dx);
+      bernstein_d<P>(uy, sm.by, dy);
+      bernstein_d<P>(uz, sm.bz, dz);
+      float f[NCOMP], g[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int q = 0; q < NCOMP; ++q) {
+        float o[4];
+        contract_grad<P>(c + q * NB, sm.bx, sm.by, sm.bz, dx, dy, dz, o);
+        f[q] = o[0];
+        const float w = NCOMP == 1 ? 1.0f : o[0];      // grad |f| is parallel to sum_q f_q grad f_q
+#pragma unroll
+        for (int a = 0; a < 3; ++a) g[a] = fmaf(w, o[1 + a] * inv[a], g[a]);
+      }
+      const float l[3] = {s.shading == LR_SHADE_HEADLIGHT ? r.d[0] : s.light[0],
+                          s.shading == LR_SHADE_HEADLIGHT ? r.d[1] : s.light[1],
+                          s.shading == LR_SHADE_HEADLIGHT ? r.d[2] : s.light[2]};
+      const float I = diffuse(l, g);
+      if constexpr (COLOR == LR_COLOR_HUE) {
+        const float vm = __builtin_amdgcn_sqrtf(fmaf(f[0], f[0], fmaf(f[1], f[1], f[2] * f[2])));
+        sm.tf = transfer(lut, vm, s.vmin, s.inv_range);
+        hsv_full(hue_of(f[0], f[1]), sm.csrc);
+      } else {
+        sm.tf = transfer(lut, f[0], s.vmin, s.inv_range);
+        sm.csrc[0] = sm.tf.rgba.x;
+        sm.csrc[1] = sm.tf.rgba.y;
+        sm.csrc[2] = sm.tf.rgba.z;
+      }
+      sm.csrc[0] *= I;
+      sm.csrc[1] *= I;
+      sm.csrc[2] *= I;
+    } else if constexpr (COLOR == LR_COLOR_HUE) {
+      bernstein<P>(ux, sm.bx);
+      bernstein<P>(uy, sm.by);
+      bernstein<P>(uz, sm.bz);
       const float fx = contract<P>(c, sm.bx, sm.by, sm.bz);
       const float fy = contract<P>(c + NB, sm.bx, sm.by, sm.bz);
       const float fz = contract<P>(c + 2 * NB, sm.bx, sm.by, sm.bz);
@@ -413,6 +520,9 @@ __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, V
       sm.tf = transfer(lut, vm, s.vmin, s.inv_range);
       hsv_full(hue_of(fx, fy), sm.csrc);
     } else {
+      bernstein<P>(ux, sm.bx);
+      bernstein<P>(uy, sm.by);
+      bernstein<P>(uz, sm.bz);
       const float v = contract<P>(c, sm.bx, sm.by, sm.bz);
       sm.tf = transfer(lut, v, s.vmin, s.inv_range);
       sm.csrc[0] = sm.tf.rgba.x;
@@ -489,7 +599,7 @@ __device__ inline bool locate(const ViewsK& vk, int64_t g, int& v, int& px, int&
   return px < vk.v[v].width && py < vk.v[v].height;
 }
 
-template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK>
+template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK, int SH>
 __global__ __launch_bounds__(kThreads) void render_kernel(const SceneK s, const ViewsK vk, float4* __restrict__ rgba,
                                                          uint32_t* __restrict__ nsamples) {
   __shared__ float4 lut[256];
@@ -505,12 +615,12 @@ __global__ __launch_bounds__(kThreads) void render_kernel(const SceneK s, const 
     int n = 0;
     __device__ inline void finish(int k) { n = k; }
   } vis;
-  if (r.hit) march<P, NCOMP, CT, MODE, COLOR, LK>(s, r, lut, vis);
+  if (r.hit) march<P, NCOMP, CT, MODE, COLOR, LK, SH>(s, r, lut, vis);
   rgba[o] = make_float4(vis.C[0], vis.C[1], vis.C[2], 1.0f - vis.T);
   if (nsamples) nsamples[o] = (uint32_t)vis.n;
 }
 
-template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK>
+template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK, int SH>
 __global__ __launch_bounds__(64) void trace_kernel(const SceneK s, const lr_view view, const int32_t* __restrict__ pix,
                                                    int64_t n, int32_t max_out, float* t_out, int32_t* e_out,
                                                    float* ds_out, int32_t* count) {
@@ -528,7 +638,7 @@ __global__ __launch_bounds__(64) void trace_kernel(const SceneK s, const lr_view
   int taken = 0;
   if (i >= 0 && j >= 0 && i < view.width && j < view.height) {
     const Ray r = make_ray(view, i, j);
-    if (r.hit) march<P, NCOMP, CT, MODE, COLOR, LK>(s, r, lut, vis);
+    if (r.hit) march<P, NCOMP, CT, MODE, COLOR, LK, SH>(s, r, lut, vis);
     taken = vis.k;
   }
   count[k] = taken;
@@ -759,6 +869,14 @@ lr_status make_scene(const lr_scene* sc, SceneK& s, bool need_forest = true) {
   if (sc->lookup != LR_LOOKUP_FOREST && sc->lookup != LR_LOOKUP_OCTREE)
     return fail(LR_EINVAL, "lookup must be LR_LOOKUP_FOREST or LR_LOOKUP_OCTREE");
   if (sc->n_nodes >= (int64_t)LR_LEAF) return fail(LR_EINVAL, "too many look-up nodes");
+  if (sc->shading != LR_SHADE_NONE && sc->shading != LR_SHADE_DIRECTIONAL && sc->shading != LR_SHADE_HEADLIGHT)
+    return fail(LR_EINVAL, "shading must be LR_SHADE_NONE, LR_SHADE_DIRECTIONAL or LR_SHADE_HEADLIGHT");
+  if (sc->shading != LR_SHADE_NONE && sc->lookup != LR_LOOKUP_FOREST)
+    return fail(LR_EINVAL, "shading is implemented with the forest look-up");
+  const double ln = std::sqrt((double)sc->light[0] * sc->light[0] + (double)sc->light[1] * sc->light[1] +
+                              (double)sc->light[2] * sc->light[2]);
+  if (sc->shading == LR_SHADE_DIRECTIONAL && !(ln > 0.0 && std::isfinite(ln)))
+    return fail(LR_EINVAL, "directional shading needs a finite non-zero light vector");
   if (sc->lookup == LR_LOOKUP_FOREST)
     for (int d = 0; d < 3; ++d)
       if (!lrvr::is_pow2(sc->blocks[d]) || sc->blocks[d] > 512) return fail(LR_ENOTPOW2, "blocks must be powers of two <= 512");
@@ -774,6 +892,8 @@ lr_status make_scene(const lr_scene* sc, SceneK& s, bool need_forest = true) {
   s.n_nodes = sc->n_nodes;
   s.stride = lr_bezier_stride(sc->p, sc->ncomp, sc->bezier_dtype);
   s.lookup = sc->lookup;
+  s.shading = sc->shading;
+  for (int a = 0; a < 3; ++a) s.light[a] = sc->shading == LR_SHADE_DIRECTIONAL ? (float)(sc->light[a] / ln) : 0.0f;
   const bool oct = sc->lookup == LR_LOOKUP_OCTREE;
   s.bx = oct ? 1 : sc->blocks[0];
   s.by = oct ? 1 : sc->blocks[1];
@@ -817,12 +937,17 @@ int64_t pack_views(const lr_view* views, int32_t n, ViewsK& vk) {
 
 template <int P, int NCOMP, typename CT, int MODE, int COLOR>
 void launch_render(const SceneK& s, const ViewsK& vk, int64_t nblk, float* rgba, uint32_t* ns, hipStream_t st) {
-  if (s.lookup == LR_LOOKUP_OCTREE)
-    hipLaunchKernelGGL((render_kernel<P, NCOMP, CT, MODE, COLOR, LR_LOOKUP_OCTREE>), dim3((unsigned)nblk),
-                       dim3(kThreads), 0, st, s, vk, reinterpret_cast<float4*>(rgba), ns);
+  // Variants: forest or octree look-up without shading; forest with shading.
+  float4* out = reinterpret_cast<float4*>(rgba);
+  if (s.shading != LR_SHADE_NONE)
+    hipLaunchKernelGGL((render_kernel<P, NCOMP, CT, MODE, COLOR, LR_LOOKUP_FOREST, 1>), dim3((unsigned)nblk),
+                       dim3(kThreads), 0, st, s, vk, out, ns);
+  else if (s.lookup == LR_LOOKUP_OCTREE)
+    hipLaunchKernelGGL((render_kernel<P, NCOMP, CT, MODE, COLOR, LR_LOOKUP_OCTREE, 0>), dim3((unsigned)nblk),
+                       dim3(kThreads), 0, st, s, vk, out, ns);
   else
-    hipLaunchKernelGGL((render_kernel<P, NCOMP, CT, MODE, COLOR, LR_LOOKUP_FOREST>), dim3((unsigned)nblk),
-                       dim3(kThreads), 0, st, s, vk, reinterpret_cast<float4*>(rgba), ns);
+    hipLaunchKernelGGL((render_kernel<P, NCOMP, CT, MODE, COLOR, LR_LOOKUP_FOREST, 0>), dim3((unsigned)nblk),
+                       dim3(kThreads), 0, st, s, vk, out, ns);
 }
 
 template <int P, int NCOMP, int COLOR>
@@ -849,12 +974,15 @@ template <int P, int NCOMP, typename CT, int MODE, int COLOR>
 void launch_trace(const SceneK& s, const lr_view& v, const int32_t* pix, int64_t n, int32_t m, float* t, int32_t* e,
                   float* ds, int32_t* cnt, hipStream_t st) {
   const dim3 grid((unsigned)((n + 63) / 64));
-  if (s.lookup == LR_LOOKUP_OCTREE)
-    hipLaunchKernelGGL((trace_kernel<P, NCOMP, CT, MODE, COLOR, LR_LOOKUP_OCTREE>), grid, dim3(64), 0, st, s, v, pix, n,
-                       m, t, e, ds, cnt);
+  if (s.shading != LR_SHADE_NONE)
+    hipLaunchKernelGGL((trace_kernel<P, NCOMP, CT, MODE, COLOR, LR_LOOKUP_FOREST, 1>), grid, dim3(64), 0, st, s, v, pix,
+                       n, m, t, e, ds, cnt);
+  else if (s.lookup == LR_LOOKUP_OCTREE)
+    hipLaunchKernelGGL((trace_kernel<P, NCOMP, CT, MODE, COLOR, LR_LOOKUP_OCTREE, 0>), grid, dim3(64), 0, st, s, v, pix,
+                       n, m, t, e, ds, cnt);
   else
-    hipLaunchKernelGGL((trace_kernel<P, NCOMP, CT, MODE, COLOR, LR_LOOKUP_FOREST>), grid, dim3(64), 0, st, s, v, pix, n,
-                       m, t, e, ds, cnt);
+    hipLaunchKernelGGL((trace_kernel<P, NCOMP, CT, MODE, COLOR, LR_LOOKUP_FOREST, 0>), grid, dim3(64), 0, st, s, v, pix,
+                       n, m, t, e, ds, cnt);
 }
 
 template <int P>
@@ -951,6 +1079,7 @@ LR_API lr_status lr_render_backward(const lr_scene* sc, const lr_view* views, in
   if (sc->ncomp != 1 || sc->color_mode != LR_COLOR_LUT || sc->bezier_dtype != LR_F32)
     return fail(LR_EINVAL, "lr_render_backward: scalar fields with FP32 blocks only");
   if (sc->lookup != LR_LOOKUP_FOREST) return fail(LR_EINVAL, "lr_render_backward: forest look-up only");
+  if (sc->shading != LR_SHADE_NONE) return fail(LR_EINVAL, "lr_render_backward: no shading");
   if (!views || n_views < 1 || !rgba_fwd || !grad_rgba || !grad_bezier || !grad_lut)
     return fail(LR_EINVAL, "lr_render_backward: null pointer or no views");
   for (int i = 0; i < n_views; ++i)

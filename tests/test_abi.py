@@ -34,7 +34,7 @@ def test_exports_every_declared_symbol():
 
 
 def test_struct_sizes():
-    assert ctypes.sizeof(L.ViewC) == 80 and ctypes.sizeof(L.SceneC) == 128
+    assert ctypes.sizeof(L.ViewC) == 80 and ctypes.sizeof(L.SceneC) == 144
     assert P.bezier_stride((2, 2, 2), 1, L.LR_F32) == 28
     assert P.bezier_stride((3, 3, 3), 1, L.LR_F32) == 64
     assert P.bezier_stride((2, 2, 2), 3, L.LR_F32) == 84
@@ -171,6 +171,9 @@ def _scene_struct(**kw):
     s.n_fixed_steps = kw.get("n_fixed_steps", 0)
     s.color_mode = kw.get("color_mode", L.LR_COLOR_LUT)
     s.max_samples = kw.get("max_samples", 100)
+    s.lookup = kw.get("lookup", L.LR_LOOKUP_FOREST)
+    s.shading = kw.get("shading", L.LR_SHADE_NONE)
+    s.light[:] = kw.get("light", (0.0, 0.0, 1.0))
     return s
 
 
@@ -185,6 +188,10 @@ def _scene_struct(**kw):
     ({"alpha_clamp": 1.0}, L.LR_EINVAL),
     ({"step_mode": L.LR_STEP_FIXED, "n_fixed_steps": 0}, L.LR_EINVAL),
     ({"max_samples": 0}, L.LR_EINVAL),
+    ({"lookup": 2}, L.LR_EINVAL),
+    ({"shading": 3}, L.LR_EINVAL),
+    ({"shading": L.LR_SHADE_DIRECTIONAL, "light": (0.0, 0.0, 0.0)}, L.LR_EINVAL),
+    ({"shading": L.LR_SHADE_HEADLIGHT, "lookup": L.LR_LOOKUP_OCTREE}, L.LR_EINVAL),
 ])
 def test_render_rejects_bad_scene(kw, status):
     import lrgen
@@ -222,6 +229,11 @@ def test_backward_rejects_vector_and_f16():
     assert lib.lr_render_backward(ctypes.byref(s), arr, 1, f, f, f, f, None) == L.LR_EINVAL
     s = _scene_struct(dtype=L.LR_F16)
     assert lib.lr_render_backward(ctypes.byref(s), arr, 1, f, f, f, f, None) == L.LR_EINVAL
+    s = _scene_struct(lookup=L.LR_LOOKUP_OCTREE)
+    assert lib.lr_render_backward(ctypes.byref(s), arr, 1, f, f, f, f, None) == L.LR_EINVAL
+    s = _scene_struct(shading=L.LR_SHADE_HEADLIGHT)
+    assert lib.lr_render_backward(ctypes.byref(s), arr, 1, f, f, f, f, None) == L.LR_EINVAL
+    assert b"shading" in lib.lr_last_error()
 
 
 def test_lookup_and_extract_validate_first():

@@ -1,0 +1,82 @@
+"""Gradient-based local illumination (Sec. 4.1) on the GPU against the FP64
+oracle: the value and the gradient come from the same Bezier block on the GPU
+and from the LR B-splines (Cox-de Boor and its derivative) in the oracle."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+from conftest import workload
+from gpu_util import TOL_F32, oracle_parts, peak_rel, resized, say, scene
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _oracle(name, view, shading, light, ii=None, jj=None):
+    from oracle import render as orr
+    wl = workload(name)
+    ev, ei = oracle_parts(name)
+    if ii is None:
+        jj, ii = np.meshgrid(np.arange(view.height), np.arange(view.width), indexing="ij")
+        ii, jj = ii.ravel(), jj.ravel()
+    return orr.render_view(wl, view, orr.LRField(ev), eidx=ei, ii=ii, jj=jj, shading=shading, light=light)
+
+
+def _gpu_render(name, view, shading, light, blocks=64):
+    import paper_1707_01170_amd as P
+    wl, sc = scene(name, blocks=blocks)
+    prm = dataclasses.replace(P.RenderParams.of(wl), shading=shading, light=light)
+    rgba, _, ns = P.render(P.Scene(sc.volume, prm), [view], nsamples=True)
+    torch.cuda.synchronize()
+    return rgba.cpu().numpy(), ns.cpu().numpy()
+
+
+@pytest.mark.parametrize("name,w,h,shading", [
+    ("config1", 0, 0, "directional"),
+    ("config5", 96, 72, "headlight"),
+    ("config2", 64, 48, "headlight"),
+    ("config3", 80, 45, "directional"),
+])
+def test_shaded_images_match_oracle(name, w, h, shading):
+    say("[gpu] shading", name, shading)
+    wl = workload(name)
+    view = wl.views[0] if w == 0 else resized(wl.views[0], w, h)
+    light = (0.48, -0.6, 0.64)
+    got, ns = _gpu_render(name, view, shading, light)
+    ref, rns, _ = _oracle(name, view, shading, light)
+    err, rms = peak_rel(got, ref)
+    plain, _ = _gpu_render(name, view, "none", light)
+    changed = np.abs(plain[:, :3] - got[:, :3]).max() / max(np.abs(plain).max(), 1e-9)
+    say("shaded %s %s: peak-rel %.3e rms %.3e (shading changed the image by %.3f)" % (name, shading, err, rms, changed))
+    assert np.array_equal(ns > 0, rns > 0)
+    assert changed > 0.05
+    assert err <= TOL_F32
+
+
+def test_linear_field_constant_intensity():
+    """A linear field has one normal: the shaded image is I times the plain one
+    in colour and identical in opacity (directional light)."""
+    import lrgen
+    import paper_1707_01170_amd as P
+    s = lrgen.tensor_spline((2, 2, 2), (4, 4, 4))
+    g = s.greville()
+    a = np.array([0.3, -0.2, 0.25])
+    s = s.with_coef((0.2 + g @ a)[:, None])
+    view = lrgen.sphere_view([0.3, -0.8, 0.5], 40, 30)
+    wl = lrgen.Workload("lin", s, lrgen.default_lut(), -0.5, 1.2, "adaptive", 0, "lut", [view])
+    vol = P.Volume(s, blocks=4)
+    light = (0.6, 0.0, 0.8)
+    I = max(0.4, abs(np.dot(a, light)) / np.linalg.norm(a))
+    prm = P.RenderParams.of(wl)
+    plain, _, _ = P.render(P.Scene(vol, prm), [view])
+    lit, _, _ = P.render(P.Scene(vol, dataclasses.replace(prm, shading="directional", light=light)), [view])
+    plain, lit = plain.cpu().numpy(), lit.cpu().numpy()
+    assert np.array_equal(plain[:, 3], lit[:, 3])
+    assert np.abs(lit[:, :3] - I * plain[:, :3]).max() <= 1e-5 * np.abs(plain).max()
