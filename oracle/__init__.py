@@ -16,6 +16,9 @@ Modules
            fixed) and front-to-back compositing (Alg. 2, Eq. 3)
   grad     reverse-mode derivative of the Bezier-parameterised render and
            central finite differences
+  streamline  explicit Runge-Kutta streamlines with the Eq. 4 heuristic step,
+           constant or embedded error-controlled steps, and the error metric
+           Eq. 7 against a small-step RKF5 reference (Sec. 5)
 
 Pins (tests/test_oracle_*.py) tie every function to something other than
 itself: partition of unity, polynomial reproduction through refinement,

@@ -185,3 +185,24 @@ def test_illumination_unnormalised(monkeypatch):
 
     monkeypatch.setattr(orr, "illumination", bad)
     _fails(pins.test_illumination_of_linear_field, "lut")
+
+
+def test_rk4_weight_misprinted(monkeypatch):
+    import oracle.streamline as ost
+    import test_oracle_streamlines as sp
+    bad = dict(ost.TABLEAUS["rk4"])
+    bad["b"] = np.array([1 / 6, 1 / 6, 1 / 2, 1 / 6])          # sums to 1, wrong order
+    monkeypatch.setitem(ost.TABLEAUS, "rk4", bad)
+    _fails(sp.test_convergence_order, "rk4", 4)
+
+
+def test_heuristic_step_wrong_degree(monkeypatch):
+    import oracle.streamline as ost
+    import test_oracle_streamlines as sp
+    good = ost.heuristic_ds
+
+    def bad(elem_box, eidx, x, p_max):
+        return good(elem_box, eidx, x, p_max - 1)
+
+    monkeypatch.setattr(ost, "heuristic_ds", bad)
+    _fails(sp.test_lr_streamline_converges_to_exact)
