@@ -285,6 +285,21 @@ def main():
     times = np.array([a.elapsed_time(b) for a, b in ev])      # ms, per launch, on the launch stream
     log("frame ms: mean %.3f p50 %.3f p99 %.3f; wall %.3f s" % (times.mean(), np.percentile(times, 50),
                                                                np.percentile(times, 99), wall))
+    # local illumination (Sec. 4.1): the same frame with a head light
+    import dataclasses
+    sc_lit = P.Scene(vol, dataclasses.replace(P.RenderParams.of(wl), shading="headlight"))
+    for _ in range(2):
+        P.render(sc_lit, views, out=out)
+    la, lb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    la.record(stream)
+    for _ in range(args.steps):
+        P.render(sc_lit, views, out=out)
+    lb.record(stream)
+    torch.cuda.synchronize()
+    lit_ms = la.elapsed_time(lb) / args.steps
+    log("illuminated frame %.3f ms (%.2fx the plain frame)" % (lit_ms, lit_ms / times.mean()))
+    illumination = {"shading": "headlight, I = max(0.4, |l.n|)", "ms_per_frame": lit_ms,
+                    "ratio_to_plain": lit_ms / times.mean()}
     if args.copy_calib:
         n = 256 << 20
         src = torch.ones(n // 4, dtype=torch.float32, device=dev)
@@ -330,6 +345,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "adjoint": adjoint,
+        "illumination": illumination,
     }
     if sweep is not None:
         res["lookup_sweep"] = sweep

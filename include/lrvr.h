@@ -304,6 +304,60 @@ lr_status lr_trace_rays(const lr_scene* sc, const lr_view* view, const int32_t* 
                         int32_t max_out, float* t_out, int32_t* elem_out, float* ds_out,
                         int32_t* count, void* stream);
 
+/* --------------------------------------------------------------- streamlines
+ * Sec. 5: a streamline from seed x0 solves dx/dt = f(x), x(0) = x0 (Eq. 5),
+ * here by an explicit Runge-Kutta method (Eq. 6) with published tableaus:
+ * k_i = f(x_n + h sum_{j<i} a_ij k_j), x_{n+1} = x_n + h sum_i b_i k_i. */
+#define LR_RK1 0      /* explicit Euler */
+#define LR_RK2 1      /* midpoint */
+#define LR_RK3 2      /* Kutta's third order */
+#define LR_RK4 3      /* classic fourth order */
+#define LR_RK4_38 4   /* 3/8 rule */
+#define LR_RKF5 5     /* Fehlberg's pair, fifth-order weights */
+#define LR_HE 6       /* Heun-Euler 2(1) */
+#define LR_BS 7       /* Bogacki-Shampine 3(2) */
+#define LR_RKF45 8    /* Fehlberg 4(5), fifth order propagated */
+
+/* Step sizes.  HEURISTIC (Sec. 5.2): h = base * 2^-d * min side of the element
+ * holding x_n, the Eq. 4 distance used as the time step (the element is found
+ * at x_n rounded to FP32).  CONSTANT: h = base.  EMBEDDED (LR_HE, LR_BS,
+ * LR_RKF45): the higher-order solution is kept; err = |x_high - x_low|_2; a
+ * step is accepted if err <= tol, or h <= 1e-14, or after 64 rejections; a
+ * rejected step retries with h * max(0.2, 0.9 (tol/err)^(1/q)) (at least
+ * 1e-14); the next step is h * min(5, max(0.2, 0.9 (tol/err)^(1/q))), q the
+ * propagated order (5 if err = 0); the first h is the heuristic step at the seed. */
+#define LR_STREAM_HEURISTIC 0
+#define LR_STREAM_CONSTANT 1
+#define LR_STREAM_EMBEDDED 2
+
+/* Sec. 5.6: MIXED keeps x, t, h and the stage sums in FP64 and evaluates the
+ * field in FP32; SINGLE does everything in FP32. */
+#define LR_PREC_MIXED 0
+#define LR_PREC_SINGLE 1
+
+typedef struct {
+    int32_t method;        /* LR_RK1 .. LR_RKF45 */
+    int32_t step_mode;     /* LR_STREAM_* */
+    int32_t precision;     /* LR_PREC_MIXED or LR_PREC_SINGLE */
+    int32_t max_samples;   /* points stored per line, the seed included, >= 1 */
+    double base;           /* step factor (see the step sizes), > 0 */
+    double t_end;          /* time limit, > 0: the last step is shortened to land on it */
+    double tol;            /* local error tolerance of LR_STREAM_EMBEDDED, > 0 */
+} lr_stream_params;
+
+/* The compute stage of Sec. 5.3 for n seeds (device double [n][3]).
+ * The field is the scene's 3-component volume (FP32 blocks, either look-up
+ * structure; the table and shading fields are not used).  Stage positions are
+ * clamped to [0,1]^3 before evaluation.  A line ends when t reaches t_end,
+ * when a step would leave [0,1]^3 (that step is not taken) or after
+ * max_samples points.
+ * points  device float [n][max_samples][4]: (x, y, z, 1) for the points of the
+ *         line, (0, 0, 0, 0) after its end
+ * times   optional device double [n][max_samples]: t of each point (0 after the end)
+ * count   optional device int32 [n]: points stored */
+lr_status lr_streamlines(const lr_scene* sc, const lr_stream_params* prm, const double* seeds, int64_t n,
+                         float* points, double* times, int32_t* count, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,5 +5,5 @@ Python API: api (Volume, Scene, render, RenderFunction, ExtractFunction, trace,
 lookup).
 """
 from .api import (ExtractFunction, Forest, Octree, RenderFunction, RenderParams, Scene, Volume, bezier_stride, lookup, render,  # noqa: F401
-                  render_backward, support_csr, trace, unpack)
+                  render_backward, streamlines, support_csr, trace, unpack)
 from ._build import build  # noqa: F401

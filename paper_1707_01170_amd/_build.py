@@ -36,9 +36,34 @@ def _torch_lib_dir():
 
 
 def build(verbose: bool = False) -> str:
+    """Compiles every source to an object (in parallel) and links the shared
+    library; each object carries its own gfx950 code object."""
+    from concurrent.futures import ThreadPoolExecutor
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
+    objdir = os.path.join(HERE, "_obj")
+    os.makedirs(objdir, exist_ok=True)
+    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+
+    def compile_one(src):
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        cmd = ["hipcc"] + compile_flags + ["-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), file=sys.stderr)
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+        return obj, r.returncode, r.stdout
+
+    jobs = max(1, min(len(srcs), os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(jobs) as ex:
+        results = list(ex.map(compile_one, srcs))
+    failed = [(o, out) for o, rc, out in results if rc != 0]
+    for _, _, out in results:
+        out = "\n".join(l for l in out.splitlines() if "packed-fp32-ops" not in l)
+        if out.strip():
+            print(out, file=sys.stderr)
+    if failed:
+        raise RuntimeError("HIP compilation failed: " + ", ".join(os.path.basename(o) for o, _ in failed))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["hipcc"] + HIPCC_FLAGS + srcs + ["-o", tmp]
+    cmd = ["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC"] + [o for o, _, _ in results] + ["-o", tmp]
     tl = _torch_lib_dir()
     if tl:
         cmd += ["-L" + tl, "-Wl,-rpath," + tl, "-lamdhip64"]

@@ -13,6 +13,9 @@ LR_COLOR_LUT, LR_COLOR_HUE = 0, 1
 LR_PERSP, LR_ORTHO = 0, 1
 LR_LOOKUP_FOREST, LR_LOOKUP_OCTREE = 0, 1
 LR_SHADE_NONE, LR_SHADE_DIRECTIONAL, LR_SHADE_HEADLIGHT = 0, 1, 2
+RK_METHODS = {"rk1": 0, "rk2": 1, "rk3": 2, "rk4": 3, "rk4_38": 4, "rkf5": 5, "he": 6, "bs": 7, "rkf45": 8}
+LR_STREAM_HEURISTIC, LR_STREAM_CONSTANT, LR_STREAM_EMBEDDED = 0, 1, 2
+LR_PREC_MIXED, LR_PREC_SINGLE = 0, 1
 LR_LEAF = 0x80000000
 LR_MAX_VIEWS_PER_LAUNCH = 16
 
@@ -50,6 +53,12 @@ class ViewC(ctypes.Structure):
                 ("up", _c_f32 * 3), ("tx", _c_f32), ("ty", _c_f32)]
 
 
+class StreamParams(ctypes.Structure):
+    _fields_ = [("method", _c_i32), ("step_mode", _c_i32), ("precision", _c_i32), ("max_samples", _c_i32),
+                ("base", _c_f64), ("t_end", _c_f64), ("tol", _c_f64)]
+
+
+assert ctypes.sizeof(StreamParams) == 40
 assert ctypes.sizeof(KdNode) == 16 and ctypes.sizeof(ViewC) == 80 and ctypes.sizeof(SceneC) == 144
 assert ctypes.sizeof(ForestStats) == 48 and ctypes.sizeof(LRSplineDev) == 88
 
@@ -72,6 +81,8 @@ SIGNATURES = {
     "lr_extract_bezier_backward": (_c_i32, [ctypes.POINTER(LRSplineDev), _c_i32, _vp, _vp, _vp]),
     "lr_render": (_c_i32, [ctypes.POINTER(SceneC), ctypes.POINTER(ViewC), _c_i32, _vp, _vp, _vp]),
     "lr_render_backward": (_c_i32, [ctypes.POINTER(SceneC), ctypes.POINTER(ViewC), _c_i32, _vp, _vp, _vp, _vp, _vp]),
+    "lr_streamlines": (_c_i32, [ctypes.POINTER(SceneC), ctypes.POINTER(StreamParams), _vp, _c_i64, _vp, _vp, _vp,
+                                _vp]),
     "lr_trace_rays": (_c_i32, [ctypes.POINTER(SceneC), ctypes.POINTER(ViewC), _vp, _c_i64, _c_i32, _vp, _vp, _vp,
                                _vp, _vp]),
 }

@@ -361,6 +361,30 @@ def lookup(volume: Volume, points) -> torch.Tensor:
     return out
 
 
+def streamlines(scene: Scene, seeds, method: str = "rk4", step: str = "heuristic", precision: str = "mixed",
+                base: float = 1.0, t_end: float = 1.0, tol: float = 1e-6, max_samples: int = 256):
+    """Streamlines of the scene's 3-component field from seeds [n, 3] (Sec. 5).
+    Returns (points [n, max_samples, 4] float32 (x, y, z, active),
+    times [n, max_samples] float64, count [n] int32)."""
+    dev = scene.volume.device
+    sd = torch.as_tensor(np.asarray(seeds, dtype=np.float64).reshape(-1, 3)).to(dev).contiguous()
+    n = sd.shape[0]
+    pts = torch.empty((n, max_samples, 4), dtype=torch.float32, device=dev)
+    tim = torch.empty((n, max_samples), dtype=torch.float64, device=dev)
+    cnt = torch.empty(n, dtype=torch.int32, device=dev)
+    prm = L.StreamParams()
+    prm.method = L.RK_METHODS[method]
+    prm.step_mode = {"heuristic": L.LR_STREAM_HEURISTIC, "constant": L.LR_STREAM_CONSTANT,
+                     "embedded": L.LR_STREAM_EMBEDDED}[step]
+    prm.precision = {"mixed": L.LR_PREC_MIXED, "single": L.LR_PREC_SINGLE}[precision]
+    prm.max_samples = int(max_samples)
+    prm.base, prm.t_end, prm.tol = float(base), float(t_end), float(tol)
+    s = scene.struct()
+    L.check(L.lib().lr_streamlines(ctypes.byref(s), ctypes.byref(prm), _ptr(sd), n, _ptr(pts), _ptr(tim), _ptr(cnt),
+                                   _stream(dev)))
+    return pts, tim, cnt
+
+
 def unpack(rgba: torch.Tensor, views: Sequence, offsets: Sequence[int]) -> List[torch.Tensor]:
     """Split a packed RGBA tensor into per-view [H, W, 4] images."""
     return [rgba[o:o + v.width * v.height].view(v.height, v.width, 4) for v, o in zip(views, offsets)]

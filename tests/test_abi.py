@@ -341,3 +341,33 @@ def test_octree_shapes_and_errors():
     f = ctypes.c_void_p(0x1000)
     assert lib.lr_lookup_octree(f, f, 1, 0, f, 5, f, None) == L.LR_EINVAL
     assert lib.lr_lookup_octree(f, f, 1, 10, f, 0, f, None) == L.LR_OK
+
+
+def test_streamlines_validate_first():
+    lib = L.lib()
+    f = ctypes.c_void_p(0x1000)
+    s = _scene_struct(ncomp=3, color_mode=L.LR_COLOR_HUE)
+
+    def prm(**kw):
+        p = L.StreamParams()
+        p.method, p.step_mode, p.precision = kw.get("method", 3), kw.get("step", 0), kw.get("prec", 0)
+        p.max_samples, p.base, p.t_end, p.tol = kw.get("max_samples", 16), kw.get("base", 1.0), 1.0, kw.get("tol", 0.0)
+        return p
+
+    def st(scene, p, n=4, seeds=f, pts=f):
+        return lib.lr_streamlines(ctypes.byref(scene), ctypes.byref(p), seeds, n, pts, None, None, None)
+    assert st(s, prm(), n=0) == L.LR_OK                             # no seeds: nothing launched
+    assert st(s, prm(), seeds=None) == L.LR_EINVAL
+    assert st(s, prm(), pts=None) == L.LR_EINVAL
+    assert st(s, prm(method=9)) == L.LR_EINVAL
+    assert st(s, prm(step=2)) == L.LR_EINVAL                        # RK4 has no embedded pair
+    assert st(s, prm(method=8, step=2)) == L.LR_EINVAL              # embedded needs tol > 0
+    assert st(s, prm(prec=2)) == L.LR_EINVAL
+    assert st(s, prm(max_samples=0)) == L.LR_EINVAL
+    assert st(s, prm(base=0.0)) == L.LR_EINVAL
+    assert st(_scene_struct(), prm()) == L.LR_EINVAL                # scalar field
+    assert b"3-component" in lib.lr_last_error()
+    s16 = _scene_struct(ncomp=3, color_mode=L.LR_COLOR_HUE, dtype=L.LR_F16)
+    assert st(s16, prm()) == L.LR_EINVAL
+    sb = _scene_struct(ncomp=3, color_mode=L.LR_COLOR_HUE, blocks=(3, 4, 4))
+    assert st(sb, prm()) == L.LR_ENOTPOW2

@@ -1,0 +1,156 @@
+"""Streamlines on the GPU (Sec. 5) against the FP64 oracle on the vortex-tube
+vector volume: constant steps point by point for all nine methods, the Eq. 4
+heuristic step sequence, embedded error control and single vs mixed
+precision through the error metric Eq. 7, look-up structures, stopping rules."""
+import numpy as np
+import pytest
+import torch
+
+from conftest import workload
+from gpu_util import oracle_parts, say, scene
+
+pytestmark = pytest.mark.gpu
+
+NAME = "config3"
+METHODS = ["rk1", "rk2", "rk3", "rk4", "rk4_38", "rkf5", "he", "bs", "rkf45"]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _seeds(n, seed=5):
+    rng = np.random.default_rng(seed)
+    r = 0.03 + 0.12 * rng.random(n)
+    a = 2 * np.pi * rng.random(n)
+    return np.stack([0.5 + r * np.cos(a), 0.5 + r * np.sin(a), 0.25 + 0.4 * rng.random(n)], 1)
+
+
+def _field():
+    ev = oracle_parts(NAME)[0]
+    return lambda x: ev.evaluate(x)
+
+
+def _gpu_lines(seeds, **kw):
+    import paper_1707_01170_amd as P
+    _, sc = scene(NAME, blocks=256)
+    pts, tim, cnt = P.streamlines(sc, seeds, **kw)
+    torch.cuda.synchronize()
+    return pts.cpu().numpy(), tim.cpu().numpy(), cnt.cpu().numpy()
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_constant_step_matches_oracle(method):
+    """Same method, same constant step: the lines agree point by point to the
+    FP32 evaluation of the field (FP64 outer loop on both sides)."""
+    from oracle import streamline as ost
+    say("[gpu] streamline constant", method)
+    seeds = _seeds(24)
+    kw = dict(method=method, step="constant", base=2.0 ** -7, t_end=0.125, max_samples=64)
+    pts, tim, cnt = _gpu_lines(seeds, **kw)
+    X, T, c = ost.integrate(_field(), seeds, method, "constant", kw["base"], kw["t_end"], kw["max_samples"])
+    assert np.array_equal(cnt, c) and np.all(c == 17)
+    for j in range(seeds.shape[0]):
+        n = c[j]
+        assert np.array_equal(tim[j, :n], T[j, :n])
+        assert np.abs(pts[j, :n, :3] - X[j, :n]).max() <= 2e-6
+        assert np.all(pts[j, :n, 3] == 1.0) and np.all(pts[j, n:] == 0.0)
+
+
+def test_heuristic_steps_match_oracle():
+    """Eq. 4 steps: the step sequence is decided on FP32 positions on both
+    sides; lines whose positions stay clear of element faces follow the same
+    sequence exactly (FP32 round-off can legitimately move a point across a
+    face, after which the two sides take different but valid steps)."""
+    from oracle import streamline as ost
+    from oracle.lookup import ElementIndex
+    say("[gpu] streamline heuristic")
+    wl = workload(NAME)
+    seeds = _seeds(48, 6)
+    kw = dict(method="rk4", step="heuristic", base=1.0, t_end=0.25, max_samples=512)
+    pts, tim, cnt = _gpu_lines(seeds, **kw)
+    X, T, c = ost.integrate(_field(), seeds, "rk4", "heuristic", 1.0, 0.25, 512,
+                            elem_box=wl.spline.elem_box, eidx=oracle_parts(NAME)[1], p_max=2)
+    same = 0
+    for j in range(seeds.shape[0]):
+        n = min(cnt[j], c[j])
+        k = int(np.argmax(tim[j, :n] != T[j, :n])) if np.any(tim[j, :n] != T[j, :n]) else n
+        assert k >= 2
+        assert np.abs(pts[j, :k, :3] - X[j, :k]).max() <= 1e-5
+        same += (k == n and cnt[j] == c[j])
+    say("heuristic: %d of %d lines identical in their step sequence, %d..%d points" % (
+        same, seeds.shape[0], cnt.min(), cnt.max()))
+    assert same >= 0.9 * seeds.shape[0]
+    assert cnt.max() > 60
+
+
+@pytest.mark.parametrize("method", ["he", "bs", "rkf45"])
+def test_embedded_error_matches_oracle(method):
+    """Embedded error control: both sides reach the same global error (Eq. 7
+    against a small-step RKF5 reference) within a factor 2."""
+    from oracle import streamline as ost
+    say("[gpu] streamline embedded", method)
+    wl = workload(NAME)
+    seeds = _seeds(12, 7)
+    f = _field()
+    tol = 1e-6
+    pts, tim, cnt = _gpu_lines(seeds, method=method, step="embedded", base=1.0, t_end=0.25, tol=tol,
+                               max_samples=4096)
+    X, T, c = ost.integrate(f, seeds, method, "embedded", 1.0, 0.25, 4096, elem_box=wl.spline.elem_box,
+                            eidx=oracle_parts(NAME)[1], p_max=2, tol=tol)
+    ref = ost.reference(f, seeds, 0.25, 2.0 ** -10)
+    e_gpu = ost.error_metric(ref, pts[:, :, :3].astype(np.float64), tim, cnt)
+    e_orc = ost.error_metric(ref, X, T, c)
+    say("embedded %s: E gpu %.3e oracle %.3e, points gpu %d oracle %d" % (method, e_gpu, e_orc, cnt.sum(), c.sum()))
+    assert np.all(np.abs(T[np.arange(12), c - 1] - 0.25) < 1e-12)
+    assert np.all(np.abs(tim[np.arange(12), cnt - 1] - 0.25) < 1e-12)
+    assert e_gpu <= 2 * e_orc + 1e-7 and e_orc <= 2 * e_gpu + 1e-7
+
+
+def test_mixed_precision_converges_where_single_stalls():
+    """Sec. 5.6: with a small base step the FP32 outer loop stops converging;
+    the FP64 outer loop with FP32 field evaluation keeps converging."""
+    from oracle import streamline as ost
+    say("[gpu] streamline precision")
+    seeds = _seeds(8, 8)
+    f = _field()
+    ref = ost.reference(f, seeds, 0.125, 2.0 ** -12)
+    errs = {}
+    for prec in ("mixed", "single"):
+        for base in (2.0 ** -7, 2.0 ** -11):
+            pts, tim, cnt = _gpu_lines(seeds, method="rk4", step="constant", precision=prec, base=base, t_end=0.125,
+                                       max_samples=4096)
+            errs[prec, base] = ost.error_metric(ref, pts[:, :, :3].astype(np.float64), tim, cnt)
+    say("precision: " + ", ".join("%s h=2^%d: %.3e" % (p, int(np.log2(b)), e) for (p, b), e in errs.items()))
+    assert errs["mixed", 2.0 ** -11] < errs["single", 2.0 ** -11] / 4
+
+
+def test_octree_lines_identical_to_forest():
+    import paper_1707_01170_amd as P
+    say("[gpu] streamline octree")
+    wl = workload(NAME)
+    vol = P.Volume(wl.spline, lookup="octree")
+    sc = P.Scene(vol, P.RenderParams.of(wl))
+    seeds = _seeds(64, 9)
+    a = P.streamlines(sc, seeds, method="rk4", base=1.0, t_end=0.5, max_samples=512)
+    b = _gpu_lines(seeds, method="rk4", base=1.0, t_end=0.5, max_samples=512)
+    torch.cuda.synchronize()
+    assert np.array_equal(a[0].cpu().numpy(), b[0]) and np.array_equal(a[2].cpu().numpy(), b[2])
+
+
+def test_stopping_rules_on_the_gpu():
+    """Time limit landed on, sample cap, domain exit (points stay in [0,1]^3),
+    inactive entries after the end."""
+    say("[gpu] streamline stopping")
+    seeds = np.concatenate([_seeds(8, 10), [[0.5, 0.5, 0.97], [0.02, 0.5, 0.5]]])
+    pts, tim, cnt = _gpu_lines(seeds, method="rk2", base=1.0, t_end=3.0, max_samples=2048)
+    for j in range(seeds.shape[0]):
+        n = cnt[j]
+        assert np.all((pts[j, :n, :3] >= 0) & (pts[j, :n, :3] <= 1)) and np.all(pts[j, n:] == 0)
+    assert cnt[8] < 2048 and tim[8, cnt[8] - 1] < 3.0       # leaves through z = 1
+    pts, tim, cnt = _gpu_lines(seeds, method="rk2", base=1.0, t_end=0.01, max_samples=2048)
+    assert np.all(np.abs(tim[np.arange(10), cnt - 1] - 0.01) <= 1e-17)
+    pts, tim, cnt = _gpu_lines(seeds, method="rk2", base=1.0, t_end=3.0, max_samples=5)
+    assert np.all(cnt == 5)
