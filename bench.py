@@ -192,6 +192,66 @@ def lookup_sweep(dev, name: str, steps: int = 10):
             "rows": rows}
 
 
+def _stream_seeds(n: int, seed: int = 3):
+    rng = np.random.default_rng(seed)
+    lo, hi = np.array([0.35, 0.35, 0.2]), np.array([0.65, 0.65, 0.8])
+    return lo + (hi - lo) * rng.random((n, 3))
+
+
+def _timed_lines(sc, seeds, reps=3, **kw):
+    import torch
+
+    import paper_1707_01170_amd as P
+    P.streamlines(sc, seeds, **kw)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        out = P.streamlines(sc, seeds, **kw)
+    b.record()
+    torch.cuda.synchronize()
+    return out, a.elapsed_time(b) / reps
+
+
+def stream_lines(sc, n_seeds: int = 16384, study: bool = False):
+    """The streamline compute stage (Sec. 5.3) on the vortex volume: RK4 with
+    the Eq. 4 heuristic step, mixed precision; accuracy by Eq. 7 against an
+    RKF5 reference with a small constant step (computed by the library)."""
+    from paper_1707_01170_amd import metrics
+    seeds = _stream_seeds(n_seeds)
+    kw = dict(method="rk4", step="heuristic", precision="mixed", base=1.0, t_end=1.0, max_samples=2048)
+    (pts, tim, cnt), ms = _timed_lines(sc, seeds, **kw)
+    steps = int((cnt.long() - 1).sum().item())
+    sub = seeds[:256]
+    ref = metrics.reference(sc, sub, 1.0, 2.0 ** -13)
+    n_sub = 256
+    E = metrics.error_metric(ref, pts[:n_sub].cpu().numpy(), tim[:n_sub].cpu().numpy(), cnt[:n_sub].cpu().numpy())
+    log("streamlines: %d seeds, RK4 heuristic mixed: %.3f ms, %d steps (%.3g steps/s, %.3g field evaluations/s), "
+        "E = %.3e" % (n_seeds, ms, steps, steps / (ms / 1e3), 4 * steps / (ms / 1e3), E))
+    res = {"workload": "vortex volume (2,2,2) x3 comps, %d seeds in [0.35,0.65]^2 x [0.2,0.8], t_end 1, "
+                       "at most 2048 points per line" % n_seeds,
+           "method": "rk4, Eq. 4 heuristic step (base 1), FP64 outer loop / FP32 field", "ms": ms, "steps": steps,
+           "steps_per_s": steps / (ms / 1e3), "field_evals_per_s": 4 * steps / (ms / 1e3),
+           "error_eq7_first256": E}
+    if study:
+        rows = []
+        cases = [(m, "heuristic", "mixed", b, None) for m in ("rk1", "rk2", "rk3", "rk4", "rk4_38", "rkf5")
+                 for b in (1.0, 0.5, 0.25)]
+        cases += [(m, "embedded", "mixed", 1.0, tol) for m in ("he", "bs", "rkf45") for tol in (1e-5, 1e-6, 1e-7, 1e-8)]
+        cases += [("rk4", "constant", prec, b, None) for prec in ("mixed", "single") for b in (2.0 ** -6, 2.0 ** -9, 2.0 ** -12)]
+        for m, step, prec, base, tol in cases:
+            (p2, t2, c2), ms2 = _timed_lines(sc, sub, reps=1, method=m, step=step, precision=prec, base=base,
+                                             t_end=1.0, tol=tol or 1e-6, max_samples=8192)
+            e2 = metrics.error_metric(ref, p2.cpu().numpy(), t2.cpu().numpy(), c2.cpu().numpy())
+            n2 = int((c2.long() - 1).sum().item())
+            rows.append({"method": m, "step": step, "precision": prec, "base": base, "tol": tol, "E": e2,
+                         "ms": ms2, "steps": n2})
+            log("  study %-7s %-9s %-6s base %-9.4g tol %-7s E %.3e  %d steps  %.2f ms"
+                % (m, step, prec, base, tol, e2, n2, ms2))
+        res["study_256_seeds"] = rows
+    return res
+
+
 def serve_stream(n_req: int, dev):
     """The request stream on the (3,3,3) blob volume with FP16 Bezier storage:
     Poisson arrivals at 200/s, square views of 256..2048, continuous batching."""
@@ -224,6 +284,8 @@ def main():
     ap.add_argument("--cpu-rays", type=int, default=32768, help="rays of the oracle CPU baseline (0: skip)")
     ap.add_argument("--copy-calib", action="store_true", help="also run a plain copy of known size (counter scale)")
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false", help="skip the adjoint step timing")
+    ap.add_argument("--stream-study", action="store_true",
+                    help="also compare every RK method / step rule / precision by the error metric Eq. 7")
     ap.add_argument("--lookup-sweep", action="store_true",
                     help="also time every look-up structure (forest sizes, octree) on the 1080p and blob workloads")
     ap.add_argument("--serve", type=int, default=1000,
@@ -308,6 +370,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log("copy calibration: 3 copies of %d bytes" % n)
+    lines = stream_lines(sc, study=args.stream_study)
     adjoint = adjoint_step(dev) if args.adjoint else None
     sweep = [lookup_sweep(dev, n) for n in ("config3", "config2")] if args.lookup_sweep else None
     serving = None
@@ -346,6 +409,7 @@ def main():
         "serving": serving,
         "adjoint": adjoint,
         "illumination": illumination,
+        "streamlines": lines,
     }
     if sweep is not None:
         res["lookup_sweep"] = sweep
