@@ -102,7 +102,7 @@ def adjoint_step(dev, steps: int = 10):
 
     import lrgen
     import paper_1707_01170_amd as P
-    wl = lrgen.cached("config5")
+    wl = lrgen.cached("scalar20k")
     vol = P.Volume(wl.spline, blocks=128, device=dev)
     sc = P.Scene(vol, P.RenderParams.of(wl))
     tgt_bez, _ = vol.extract(wl.extra["coef_target"], "f32")
@@ -258,10 +258,10 @@ def serve_stream(n_req: int, dev):
     import lrgen
     import paper_1707_01170_amd as P
     from paper_1707_01170_amd.serve import Server
-    wl = lrgen.cached("config2")
+    wl = lrgen.cached("blobs50k")
     vol = P.Volume(wl.spline, blocks=128, dtype="f16", device=dev)
     sc = P.Scene(vol, P.RenderParams.of(wl))
-    reqs = lrgen.config4_requests(n=n_req)
+    reqs = lrgen.blob_requests(n=n_req)
     warm = Server(sc, budget_bytes=2 << 30).run(reqs[:8])
     log("serving: warm-up %d requests" % warm.n)
     st = Server(sc, budget_bytes=2 << 30, n_streams=3).run(reqs)
@@ -298,7 +298,7 @@ def main():
 
     import lrgen
     log("generating workload")
-    wl = lrgen.cached("config3")
+    wl = lrgen.cached("vortex200k")
     view = wl.views[0]
     cpu = None
     if args.cpu_rays > 0:       # before any GPU initialisation (the pool forks)
@@ -372,7 +372,7 @@ def main():
         log("copy calibration: 3 copies of %d bytes" % n)
     lines = stream_lines(sc, study=args.stream_study)
     adjoint = adjoint_step(dev) if args.adjoint else None
-    sweep = [lookup_sweep(dev, n) for n in ("config3", "config2")] if args.lookup_sweep else None
+    sweep = [lookup_sweep(dev, n) for n in ("vortex200k", "blobs50k")] if args.lookup_sweep else None
     serving = None
     if args.serve > 0:
         serving = serve_stream(args.serve, dev)

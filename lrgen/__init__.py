@@ -254,8 +254,8 @@ class Workload:
     extra: dict = field(default_factory=dict)
 
 
-def _streams(config: int):
-    ss = np.random.SeedSequence(SEED_BASE + config)
+def _streams(offset: int):
+    ss = np.random.SeedSequence(SEED_BASE + offset)
     mesh, coef, noise, camera, requests = ss.spawn(5)
     return mesh, coef, noise, camera, requests
 
@@ -285,7 +285,7 @@ def _value_range_vector(c):
     return 0.0, float(np.max(np.linalg.norm(c, axis=1)))
 
 
-def config1(n_views: int = 1) -> Workload:
+def scalar_ortho64(n_views: int = 1) -> Workload:
     """(2,2,2) scalar; 4^3 mesh plus exactly 20 refinements at U[0,1]^3 points;
     c ~ U[0,1]; 64x64 orthographic view along z; fixed 256 steps per ray."""
     mesh, coef, noise, camera, _ = _streams(1)
@@ -294,10 +294,10 @@ def config1(n_views: int = 1) -> Workload:
     _refine_until(r, lambda n: rm.random((n, 3)), exact=20)
     s = r.export()
     s = s.with_coef(np.random.default_rng(coef).random((s.n_bspl, 1)))
-    return Workload("config1", s, default_lut(), 0.0, 1.0, "fixed", 256, "lut", [ortho_z_view(64)])
+    return Workload("scalar_ortho64", s, default_lut(), 0.0, 1.0, "fixed", 256, "lut", [ortho_z_view(64)])
 
 
-def config2(width: int = 1024, height: int = 1024, n_views: int = 1, target: int = 50000) -> Workload:
+def blobs50k(width: int = 1024, height: int = 1024, n_views: int = 1, target: int = 50000) -> Workload:
     """(3,3,3) scalar; 16^3 mesh refined toward 8 Gaussian blobs (centres
     U[0.2,0.8]^3, sigma 0.05) until n_elem >= 50k; c = blob sum at the Greville
     point + N(0, 0.01^2); 1024^2 perspective view, FOV 45, radius 2; adaptive step."""
@@ -320,7 +320,7 @@ def config2(width: int = 1024, height: int = 1024, n_views: int = 1, target: int
     vmin, vmax = _value_range_scalar(s.coef)
     rc = np.random.default_rng(camera)
     views = [sphere_view(u, width, height) for u in random_directions(rc, n_views)]
-    return Workload("config2", s, default_lut(), vmin, vmax, "adaptive", 0, "lut", views,
+    return Workload("blobs50k", s, default_lut(), vmin, vmax, "adaptive", 0, "lut", views,
                     extra={"blob_centres": mu})
 
 
@@ -331,7 +331,7 @@ def vortex(x: np.ndarray) -> np.ndarray:
     return np.stack([-dy * w, dx * w, 0.2 * w], axis=1)
 
 
-def config3(width: int = 1920, height: int = 1080, n_views: int = 1, target: int = 200000) -> Workload:
+def vortex200k(width: int = 1920, height: int = 1080, n_views: int = 1, target: int = 200000) -> Workload:
     """(2,2,2) 3-vector; 32^3 mesh refined along the vortex tube x=y=1/2 (seed
     points (1/2+dx, 1/2+dy, z), d ~ N(0, 0.1^2 I), z ~ U[0,1]) until n_elem >=
     200k; c = vortex(Greville) + N(0, 0.01^2 I); |v| through the LUT opacity,
@@ -353,10 +353,10 @@ def config3(width: int = 1920, height: int = 1080, n_views: int = 1, target: int
     vmin, vmax = _value_range_vector(s.coef)
     rc = np.random.default_rng(camera)
     views = [sphere_view(u, width, height) for u in random_directions(rc, n_views)]
-    return Workload("config3", s, default_lut(), vmin, vmax, "adaptive", 0, "hue", views)
+    return Workload("vortex200k", s, default_lut(), vmin, vmax, "adaptive", 0, "hue", views)
 
 
-RESOLUTIONS_4 = (256, 512, 1024, 2048)
+SERVING_RESOLUTIONS = (256, 512, 1024, 2048)
 
 
 @dataclass
@@ -365,20 +365,20 @@ class Request:
     view: View
 
 
-def config4_requests(n: int = 1000, rate_hz: float = 200.0) -> List[Request]:
-    """Poisson request stream on the config-2 volume: inter-arrival times
+def blob_requests(n: int = 1000, rate_hz: float = 200.0) -> List[Request]:
+    """Poisson request stream on the blobs50k volume: inter-arrival times
     Exp(mean 1/rate), square resolutions drawn uniformly from 256..2048."""
     _, _, _, camera, requests = _streams(4)
     rq = np.random.default_rng(requests)
     gaps = rq.exponential(1.0 / rate_hz, size=n)
-    res = rq.integers(0, len(RESOLUTIONS_4), size=n)
+    res = rq.integers(0, len(SERVING_RESOLUTIONS), size=n)
     dirs = random_directions(np.random.default_rng(camera), n)
     t = np.cumsum(gaps)
-    return [Request(float(t[k]), sphere_view(dirs[k], RESOLUTIONS_4[res[k]], RESOLUTIONS_4[res[k]]))
+    return [Request(float(t[k]), sphere_view(dirs[k], SERVING_RESOLUTIONS[res[k]], SERVING_RESOLUTIONS[res[k]]))
             for k in range(n)]
 
 
-def config5(width: int = 512, height: int = 512, n_views: int = 4, target: int = 20000) -> Workload:
+def scalar20k(width: int = 512, height: int = 512, n_views: int = 4, target: int = 20000) -> Workload:
     """(2,2,2) scalar; 16^3 mesh with U[0,1]^3 refinements until n_elem >= 20k;
     coefficient set A ~ U[0,1] (rendered, differentiated) and set B ~ U[0,1]
     (targets, in extra['coef_target']); 4 perspective views 512^2; adaptive."""
@@ -392,7 +392,7 @@ def config5(width: int = 512, height: int = 512, n_views: int = 4, target: int =
     b = np.random.default_rng(cb).random((s.n_bspl, 1))
     rc = np.random.default_rng(camera)
     views = [sphere_view(u, width, height) for u in random_directions(rc, n_views)]
-    return Workload("config5", s.with_coef(a), default_lut(), 0.0, 1.0, "adaptive", 0, "lut", views,
+    return Workload("scalar20k", s.with_coef(a), default_lut(), 0.0, 1.0, "adaptive", 0, "lut", views,
                     extra={"coef_target": b})
 
 
@@ -417,7 +417,7 @@ def small_random(p=(2, 2, 2), n=(4, 4, 4), n_ref=40, seed=0, ncomp=1, dist="unif
     return s.with_coef(rng.random((s.n_bspl, ncomp)))
 
 
-CONFIGS = {1: config1, 2: config2, 3: config3, 5: config5}
+WORKLOADS = {"scalar_ortho64": scalar_ortho64, "blobs50k": blobs50k, "vortex200k": vortex200k, "scalar20k": scalar20k}
 
 
 # --------------------------------------------------------------------------

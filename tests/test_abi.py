@@ -134,7 +134,7 @@ def test_forest_matches_figure():
 
 
 def test_forest_depth_stats():
-    s = workload("config1").spline
+    s = workload("scalar_ortho64").spline
     f = P.Forest.build(s.elem_box, 4)
     st = f.stats
     assert st["min_depth"] == 0 and st["max_depth"] >= 1
@@ -147,7 +147,7 @@ def test_forest_depth_stats():
 
 
 def test_support_csr_matches_oracle():
-    for s in (workload("config1").spline, lrgen.small_random(p=(3, 3, 3), n=(3, 3, 3), n_ref=40, seed=5)):
+    for s in (workload("scalar_ortho64").spline, lrgen.small_random(p=(3, 3, 3), n=(3, 3, 3), n_ref=40, seed=5)):
         ptr, idx = P.support_csr(s)
         ev = LREvaluator(s)
         for e in range(0, s.n_elem, max(1, s.n_elem // 60)):
@@ -301,7 +301,7 @@ def _leaf_depths(oc):
 
 @pytest.mark.parametrize("make", [
     lambda: lrgen.small_random(p=(2, 2, 2), n=(4, 4, 4), n_ref=80, seed=21, dist="cluster"),
-    lambda: workload("config1").spline,
+    lambda: workload("scalar_ortho64").spline,
     lambda: lrgen.small_random(p=(3, 1, 2), n=(2, 4, 8), n_ref=60, seed=22),
 ])
 def test_octree_descent_equals_scan(make):

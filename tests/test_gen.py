@@ -24,8 +24,8 @@ def _partition_check(box, n=4000, seed=0):
     find_element_scan(box, x[:300])
 
 
-def test_config1_shape():
-    w = workload("config1")
+def test_scalar_ortho64_shape():
+    w = workload("scalar_ortho64")
     s = w.spline
     assert s.p == (2, 2, 2) and s.ncomp == 1
     # 4^3 tensor mesh plus exactly 20 refinements, each adding elements
@@ -36,8 +36,8 @@ def test_config1_shape():
     _partition_check(s.elem_box)
 
 
-def test_config5_shape():
-    w = workload("config5")
+def test_scalar20k_shape():
+    w = workload("scalar20k")
     s = w.spline
     assert 20000 <= s.n_elem < 20100
     assert _fp32_exact(s.elem_box) and _fp32_exact(s.knots)
@@ -48,8 +48,8 @@ def test_config5_shape():
 
 
 def test_generator_deterministic():
-    a = lrgen.config1().spline
-    b = lrgen.config1().spline
+    a = lrgen.scalar_ortho64().spline
+    b = lrgen.scalar_ortho64().spline
     for x, y in ((a.elem_box, b.elem_box), (a.knots, b.knots), (a.gamma, b.gamma), (a.coef, b.coef)):
         assert np.array_equal(x, y)
 
@@ -94,9 +94,9 @@ def test_lut():
 
 
 def test_requests():
-    rq = lrgen.config4_requests(n=200)
+    rq = lrgen.blob_requests(n=200)
     t = np.array([r.arrival_s for r in rq])
     assert np.all(np.diff(t) > 0)
     assert 0.5 < t[-1] < 1.5                       # 200 arrivals at 200/s
     res = {r.view.width for r in rq}
-    assert res <= set(lrgen.RESOLUTIONS_4) and len(res) == 4
+    assert res <= set(lrgen.SERVING_RESOLUTIONS) and len(res) == 4

@@ -118,7 +118,7 @@ def test_fp16_blocks_same_schedule():
     import paper_1707_01170_amd as P
     from conftest import workload
     from gpu_util import resized
-    wl = workload("config2")
+    wl = workload("blobs50k")
     v16 = P.Volume(wl.spline, blocks=64, dtype="f16")
     v32 = P.Volume(wl.spline, blocks=64, dtype="f32")
     view = resized(wl.views[0], 48, 32)

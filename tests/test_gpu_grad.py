@@ -26,9 +26,9 @@ def _oracle_blocks(coef_key="A"):
     from oracle import bezier as obez
     from oracle.bspline import LREvaluator
     if coef_key not in _C:
-        wl = workload("config5")
+        wl = workload("scalar20k")
         s = wl.spline if coef_key == "A" else wl.spline.with_coef(wl.extra["coef_target"])
-        ev = oracle_parts("config5")[0] if coef_key == "A" else LREvaluator(s)
+        ev = oracle_parts("scalar20k")[0] if coef_key == "A" else LREvaluator(s)
         _C[coef_key] = obez.extract(s, ev)
     return _C[coef_key]
 
@@ -37,9 +37,9 @@ def _oracle_grad(views, pix_per_view, g_per_view):
     """Sum over views of the oracle's dL/dC and dL/dLUT for the given pixels and
     upstream gradients."""
     from oracle import grad as ograd
-    wl = workload("config5")
+    wl = workload("scalar20k")
     C = _oracle_blocks("A")
-    ei = oracle_parts("config5")[1]
+    ei = oracle_parts("scalar20k")[1]
     gb = np.zeros_like(C)
     gl = np.zeros((256, 4))
     imgs = []
@@ -62,7 +62,7 @@ def _grid(v):
 def test_backward_small_views():
     import paper_1707_01170_amd as P
     say("[gpu] backward small")
-    wl, sc = scene("config5")
+    wl, sc = scene("scalar20k")
     views = [resized(v, w, h) for v, (w, h) in zip(wl.views, [(40, 28), (33, 17), (24, 40), (48, 48)])]
     pix = [_grid(v) for v in views]
     _, _, imgs = _oracle_grad(views, pix, [None] * 4)
@@ -85,7 +85,7 @@ def test_backward_full_size_sampled():
     pixels only, which the oracle differentiates one by one."""
     import paper_1707_01170_amd as P
     say("[gpu] backward full")
-    wl, sc = scene("config5")
+    wl, sc = scene("scalar20k")
     views = wl.views
     rng = np.random.default_rng(9)
     pix, gs_sparse = [], []
@@ -118,7 +118,7 @@ def test_autograd_l2_loss():
     import paper_1707_01170_amd as P
     from oracle import grad as ograd
     say("[gpu] autograd")
-    wl, sc = scene("config5")
+    wl, sc = scene("scalar20k")
     views = [resized(v, 36, 28) for v in wl.views]
     pix = [_grid(v) for v in views]
     vol = sc.volume
@@ -133,7 +133,7 @@ def test_autograd_l2_loss():
     # oracle
     from oracle import render as orr
     Ct = _oracle_blocks("B")
-    ei = oracle_parts("config5")[1]
+    ei = oracle_parts("scalar20k")[1]
     tg_o = [orr.render_view(wl, v, orr.BezierField(wl.spline, Ct), eidx=ei, ii=ii, jj=jj)[0]
             for v, (ii, jj) in zip(views, pix)]
     _, _, imgs = _oracle_grad(views, pix, [None] * 4)
@@ -148,7 +148,7 @@ def test_autograd_l2_loss():
 
 
 # ------------------------------------------------ adjoint of the change of basis
-@pytest.mark.parametrize("case", ["config5", "vector_deg3"])
+@pytest.mark.parametrize("case", ["scalar20k", "vector_deg3"])
 def test_extraction_adjoint(case):
     """lr_extract_bezier_backward against the oracle's transpose of its own
     interpolation extraction, for a random dL/dC (FP32 and FP64 inputs)."""
@@ -157,9 +157,9 @@ def test_extraction_adjoint(case):
     from oracle import bezier as obez
     from oracle.bspline import LREvaluator
     say("[gpu] extraction adjoint %s" % case)
-    if case == "config5":
-        s = workload("config5").spline
-        ev = oracle_parts("config5")[0]
+    if case == "scalar20k":
+        s = workload("scalar20k").spline
+        ev = oracle_parts("scalar20k")[0]
         blocks = 64
     else:
         s = lrgen.small_random(p=(3, 3, 3), n=(4, 4, 4), n_ref=40, seed=31, ncomp=3)
@@ -189,7 +189,7 @@ def test_autograd_to_lr_coefficients():
     from oracle import grad as ograd
     from oracle import render as orr
     say("[gpu] autograd to LR coefficients")
-    wl, sc = scene("config5")
+    wl, sc = scene("scalar20k")
     views = [resized(v, 32, 24) for v in wl.views]
     pix = [_grid(v) for v in views]
     vol = sc.volume
@@ -202,13 +202,13 @@ def test_autograd_to_lr_coefficients():
     loss.backward()
     torch.cuda.synchronize()
     Ct = _oracle_blocks("B")
-    ei = oracle_parts("config5")[1]
+    ei = oracle_parts("scalar20k")[1]
     tg_o = [orr.render_view(wl, v, orr.BezierField(wl.spline, Ct), eidx=ei, ii=ii, jj=jj)[0]
             for v, (ii, jj) in zip(views, pix)]
     _, _, imgs = _oracle_grad(views, pix, [None] * 4)
     gs = [ograd.l2_grad(a, b) for a, b in zip(imgs, tg_o)]
     gb_o, _, _ = _oracle_grad(views, pix, gs)
-    gc_o = obez.extract_adjoint(wl.spline, oracle_parts("config5")[0], gb_o)
+    gc_o = obez.extract_adjoint(wl.spline, oracle_parts("scalar20k")[0], gb_o)
     e_c, r_c = peak_rel(coef.grad.cpu().numpy(), gc_o)
     say("autograd to c: dL/dc peak-rel %.3e rms %.3e" % (e_c, r_c))
     assert e_c <= 1e-3

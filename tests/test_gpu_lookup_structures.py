@@ -39,7 +39,7 @@ def _probe(box, seed, n=200000):
                            np.array([[1.0, 1.0, 1.0], [0.0, 0.0, 0.0], [1.0, 0.0, 0.5]])]).astype(np.float32)
 
 
-@pytest.mark.parametrize("name", ["config1", "config5", "config2"])
+@pytest.mark.parametrize("name", ["scalar_ortho64", "scalar20k", "blobs50k"])
 def test_octree_lookup_bit_exact(name):
     import paper_1707_01170_amd as P
     say("[gpu] octree lookup", name)
@@ -50,7 +50,7 @@ def test_octree_lookup_bit_exact(name):
     assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("name,blocks", [("config5", 1), ("config2", 512)])
+@pytest.mark.parametrize("name,blocks", [("scalar20k", 1), ("blobs50k", 512)])
 def test_single_tree_and_table_lookup_bit_exact(name, blocks):
     import paper_1707_01170_amd as P
     say("[gpu] forest lookup", name, blocks)
@@ -62,7 +62,7 @@ def test_single_tree_and_table_lookup_bit_exact(name, blocks):
     assert np.array_equal(got, oracle_parts(name)[1].find(pts.astype(np.float64)))
 
 
-@pytest.mark.parametrize("name", ["config5", "config3"])
+@pytest.mark.parametrize("name", ["scalar20k", "vortex200k"])
 def test_octree_schedule_bit_exact(name):
     import paper_1707_01170_amd as P
     say("[gpu] octree trace", name)
@@ -80,11 +80,11 @@ def test_octree_schedule_bit_exact(name):
 
 
 @pytest.mark.parametrize("name,w,h,other", [
-    ("config3", 1920, 1080, ("octree", 64)),
-    ("config3", 1920, 1080, ("forest", 1)),
-    ("config3", 1920, 1080, ("forest", 512)),
-    ("config2", 512, 512, ("octree", 64)),
-    ("config5", 512, 512, ("forest", 16)),
+    ("vortex200k", 1920, 1080, ("octree", 64)),
+    ("vortex200k", 1920, 1080, ("forest", 1)),
+    ("vortex200k", 1920, 1080, ("forest", 512)),
+    ("blobs50k", 512, 512, ("octree", 64)),
+    ("scalar20k", 512, 512, ("forest", 16)),
 ])
 def test_renders_identical_across_structures(name, w, h, other):
     import paper_1707_01170_amd as P
@@ -92,7 +92,7 @@ def test_renders_identical_across_structures(name, w, h, other):
     wl = workload(name)
     prm = P.RenderParams.of(wl)
     view = resized(wl.views[0], w, h)
-    a = P.render(P.Scene(_vol(name, "forest", 256 if name == "config3" else 64), prm), [view], nsamples=True)
+    a = P.render(P.Scene(_vol(name, "forest", 256 if name == "vortex200k" else 64), prm), [view], nsamples=True)
     b = P.render(P.Scene(_vol(name, *other), prm), [view], nsamples=True)
     torch.cuda.synchronize()
     assert torch.equal(a[0], b[0]) and torch.equal(a[2], b[2])
@@ -102,8 +102,8 @@ def test_renders_identical_across_structures(name, w, h, other):
 def test_octree_rejects_backward():
     import paper_1707_01170_amd as P
     from paper_1707_01170_amd import _lib as L
-    wl = workload("config5")
-    sc = P.Scene(_vol("config5", "octree"), P.RenderParams.of(wl))
+    wl = workload("scalar20k")
+    sc = P.Scene(_vol("scalar20k", "octree"), P.RenderParams.of(wl))
     view = resized(wl.views[0], 8, 8)
     rgba, _, _ = P.render(sc, [view])
     with pytest.raises(L.LRError):

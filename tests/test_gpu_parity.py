@@ -24,7 +24,7 @@ def _gpu():
 
 
 # ---------------------------------------------------------------- Alg. 1 look-up
-@pytest.mark.parametrize("name,blocks", [("config5", 16), ("config5", 64), ("config1", 1), ("config1", 4)])
+@pytest.mark.parametrize("name,blocks", [("scalar20k", 16), ("scalar20k", 64), ("scalar_ortho64", 1), ("scalar_ortho64", 4)])
 def test_lookup_bit_exact(name, blocks):
     import paper_1707_01170_amd as P
     say("[gpu] lookup", name, blocks)
@@ -48,13 +48,13 @@ def _small_vector():
     return s
 
 
-@pytest.mark.parametrize("which", ["config1", "deg3", "vector"])
+@pytest.mark.parametrize("which", ["scalar_ortho64", "deg3", "vector"])
 def test_extraction_f64_matches_oracle(which):
     import paper_1707_01170_amd as P
     from oracle import bezier as obez
     from oracle.bspline import LREvaluator
     say("[gpu] extract", which)
-    s = {"config1": lambda: workload("config1").spline,
+    s = {"scalar_ortho64": lambda: workload("scalar_ortho64").spline,
          "deg3": lambda: lrgen.small_random(p=(3, 3, 3), n=(2, 2, 2), n_ref=50, seed=32, dist="cluster"),
          "vector": _small_vector}[which]()
     vol = P.Volume(s, blocks=4, dtype="f64")
@@ -90,12 +90,12 @@ def test_extraction_rounding_is_rne():
 
 
 # ---------------------------------------------------------------- Eq. 4 schedule, bit for bit
-@pytest.mark.parametrize("name", ["config1", "config5", "config2", "config3"])
+@pytest.mark.parametrize("name", ["scalar_ortho64", "scalar20k", "blobs50k", "vortex200k"])
 def test_sample_schedule_bit_exact(name):
     import paper_1707_01170_amd as P
     say("[gpu] trace", name)
     wl, sc = scene(name)
-    view = wl.views[0] if name == "config1" else resized(wl.views[0], 96, 64)
+    view = wl.views[0] if name == "scalar_ortho64" else resized(wl.views[0], 96, 64)
     rng = np.random.default_rng(7)
     ii = rng.integers(0, view.width, 48)
     jj = rng.integers(0, view.height, 48)
@@ -123,19 +123,19 @@ def _render(sc, views, bezier=None):
     return rgba.cpu().numpy(), offs, ns.cpu().numpy()
 
 
-def test_config1_full_image():
-    say("[gpu] config1 image")
-    wl, sc = scene("config1")
+def test_scalar_ortho64_full_image():
+    say("[gpu] scalar_ortho64 image")
+    wl, sc = scene("scalar_ortho64")
     rgba, _, ns = _render(sc, wl.views)
     ii, jj = np.meshgrid(np.arange(64), np.arange(64))
-    ref, rns, _ = oracle_render("config1", wl.views[0], ii.ravel(), jj.ravel())
+    ref, rns, _ = oracle_render("scalar_ortho64", wl.views[0], ii.ravel(), jj.ravel())
     err, rms = peak_rel(rgba, ref)
-    say("config1 peak-rel max %.3e rms %.3e" % (err, rms))
+    say("scalar_ortho64 peak-rel max %.3e rms %.3e" % (err, rms))
     assert err <= TOL_F32
     assert np.array_equal(ns[rns == 256], rns[rns == 256]) and np.all(ns <= 256)
 
 
-@pytest.mark.parametrize("name,w,h", [("config5", 72, 40), ("config2", 50, 38), ("config3", 72, 41)])
+@pytest.mark.parametrize("name,w,h", [("scalar20k", 72, 40), ("blobs50k", 50, 38), ("vortex200k", 72, 41)])
 def test_small_full_images(name, w, h):
     """Whole images several tiles wide with ragged edges."""
     say("[gpu] small image", name)
@@ -150,7 +150,7 @@ def test_small_full_images(name, w, h):
     assert np.all(ns <= rns) and np.mean(ns == rns) > 0.5
 
 
-@pytest.mark.parametrize("name", ["config2", "config3", "config5"])
+@pytest.mark.parametrize("name", ["blobs50k", "vortex200k", "scalar20k"])
 def test_full_size_sampled(name):
     """The full-size launch (as benchmarked), checked on seeded pixels and one tile."""
     say("[gpu] full size", name)
@@ -173,10 +173,10 @@ def test_constant_field_closed_form():
 
     import paper_1707_01170_amd as P
     from oracle import camera as ocam
-    wl = copy.copy(workload("config5"))
+    wl = copy.copy(workload("scalar20k"))
     k = 77
     c0 = wl.vmin + (k / 255.0) * (wl.vmax - wl.vmin)
-    vol = volume("config5")
+    vol = volume("scalar20k")
     bez, _ = vol.extract(np.full_like(wl.spline.coef, c0), "f32")
     sc = P.Scene(vol, P.RenderParams.of(wl))
     view = resized(wl.views[0], 64, 48)
@@ -190,7 +190,7 @@ def test_constant_field_closed_form():
     assert np.abs(rgba[:, :3] - alpha[:, None] * lut[k, :3]).max() < 2e-5
 
 
-@pytest.mark.parametrize("name", ["config2", "config5"])
+@pytest.mark.parametrize("name", ["blobs50k", "scalar20k"])
 def test_fp16_storage(name):
     """FP16 Bezier storage with FP32 arithmetic: error stated, sanity-bounded."""
     say("[gpu] fp16", name)
@@ -210,7 +210,7 @@ def test_fp16_storage(name):
 def test_views_mixed_in_one_call():
     """Several views of mixed size in one call equal the same views alone."""
     import paper_1707_01170_amd as P
-    wl, sc = scene("config5")
+    wl, sc = scene("scalar20k")
     views = [resized(wl.views[i % 4], w, h) for i, (w, h) in enumerate([(40, 24), (17, 33), (64, 64), (8, 8)] * 5)]
     together, offs, _ = P.render(sc, views)
     together = together.cpu().numpy()
@@ -222,7 +222,7 @@ def test_views_mixed_in_one_call():
 def test_bad_input_is_rejected():
     import paper_1707_01170_amd as P
     from paper_1707_01170_amd import _lib as L
-    wl, sc = scene("config5")
+    wl, sc = scene("scalar20k")
     bad = resized(wl.views[0], 8, 8)
     bad.eye = np.array([np.nan, 0, 0], np.float32)
     with pytest.raises(L.LRError) as ex:

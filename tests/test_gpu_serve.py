@@ -33,7 +33,7 @@ def _stream(n, seed, sizes=(40, 64, 96, 128, 200)):
 def test_results_identical_alone_and_in_the_mix(dtype):
     from paper_1707_01170_amd.serve import Server, render_alone
     say("[gpu] serve mix", dtype)
-    _, sc = scene("config2", dtype=dtype)
+    _, sc = scene("blobs50k", dtype=dtype)
     reqs = _stream(60, 1)
     srv = Server(sc, budget_bytes=16 * 200 * 200 * 6, n_streams=3)
     st = srv.run(reqs, keep_images=True)
@@ -48,7 +48,7 @@ def test_results_identical_alone_and_in_the_mix(dtype):
 
 def test_tight_budget_queues_instead_of_failing():
     from paper_1707_01170_amd.serve import Server
-    _, sc = scene("config5")
+    _, sc = scene("scalar20k")
     reqs = _stream(30, 2, sizes=(128, 200))
     srv = Server(sc, budget_bytes=16 * 200 * 200 + 16, n_streams=2)   # one large request at a time
     st = srv.run(reqs)

@@ -39,10 +39,10 @@ def _gpu_render(name, view, shading, light, blocks=64):
 
 
 @pytest.mark.parametrize("name,w,h,shading", [
-    ("config1", 0, 0, "directional"),
-    ("config5", 96, 72, "headlight"),
-    ("config2", 64, 48, "headlight"),
-    ("config3", 80, 45, "directional"),
+    ("scalar_ortho64", 0, 0, "directional"),
+    ("scalar20k", 96, 72, "headlight"),
+    ("blobs50k", 64, 48, "headlight"),
+    ("vortex200k", 80, 45, "directional"),
 ])
 def test_shaded_images_match_oracle(name, w, h, shading):
     say("[gpu] shading", name, shading)

@@ -11,7 +11,7 @@ from gpu_util import oracle_parts, say, scene
 
 pytestmark = pytest.mark.gpu
 
-NAME = "config3"
+NAME = "vortex200k"
 METHODS = ["rk1", "rk2", "rk3", "rk4", "rk4_38", "rkf5", "he", "bs", "rkf45"]
 
 

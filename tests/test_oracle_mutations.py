@@ -155,7 +155,7 @@ def test_extraction_adjoint_untransposed(monkeypatch):
 
     monkeypatch.setattr(obez, "extract_adjoint", bad)
     _fails(pins.test_extraction_adjoint_brute_force)
-    _fails(pins.test_extraction_adjoint_of_point_evaluation, lambda: pins.workload("config1").spline)
+    _fails(pins.test_extraction_adjoint_of_point_evaluation, lambda: pins.workload("scalar_ortho64").spline)
 
 
 def test_extraction_adjoint_without_gamma(monkeypatch):

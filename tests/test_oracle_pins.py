@@ -21,7 +21,7 @@ from oracle.lookup import ElementIndex, find_element_scan
 
 # ---------------------------------------------------------------- P1 partition of unity
 @pytest.mark.parametrize("make", [
-    lambda: workload("config1").spline,
+    lambda: workload("scalar_ortho64").spline,
     lambda: lrgen.small_random(p=(3, 3, 3), n=(3, 3, 3), n_ref=50, seed=7, dist="cluster"),
     lambda: lrgen.small_random(p=(2, 3, 1), n=(4, 2, 5), n_ref=40, seed=8),
 ])
@@ -144,7 +144,7 @@ def test_extraction_closed_form(p, n, n_ref, dist):
 def test_extraction_matches_cox_de_boor():
     """Bernstein evaluation of the blocks = Cox-de Boor evaluation, per element;
     convex hull; local dimension >= Bezier dimension (Sec. 3.2.3)."""
-    for s in (workload("config1").spline,
+    for s in (workload("scalar_ortho64").spline,
               lrgen.small_random(p=(3, 3, 3), n=(3, 3, 3), n_ref=40, seed=4, ncomp=3)):
         ev = LREvaluator(s)
         C = obez.extract(s, ev)
@@ -259,7 +259,7 @@ def test_constant_field_closed_form(mode):
     sigma = -ln(1 - alpha_src)/xi, and C = C_src alpha, for any partition of the
     ray; Alg. 2 telescopes to it."""
     import copy
-    base = copy.copy(workload("config5"))
+    base = copy.copy(workload("scalar20k"))
     base.step_mode = "fixed" if mode == "fixed" else "adaptive"
     base.n_fixed_steps = 37
     k = 77
@@ -312,7 +312,7 @@ def test_adaptive_schedule_powers_of_two():
     """Every step is 2^-d min side(e) of the sample's element (exact in FP32
     on dyadic meshes), clipped only at the exit, and the element of each sample
     contains the sample (Eq. 4)."""
-    w = workload("config5")
+    w = workload("scalar20k")
     view = lrgen.sphere_view([0.6, 0.3, 0.7], 20, 20)
     ev = LREvaluator(w.spline)
     _, ns, recs = orr.render_view(w, view, orr.LRField(ev), record=True)
@@ -329,7 +329,7 @@ def test_adaptive_schedule_powers_of_two():
 
 
 def test_lr_and_bezier_forms_render_alike():
-    w = workload("config1")
+    w = workload("scalar_ortho64")
     ev = LREvaluator(w.spline)
     C = obez.extract(w.spline, ev)
     ii, jj = ocam.pixel_grid(w.views[0])
@@ -393,7 +393,7 @@ def test_extraction_adjoint_brute_force():
 
 
 @pytest.mark.parametrize("make", [
-    lambda: workload("config1").spline,
+    lambda: workload("scalar_ortho64").spline,
     lambda: lrgen.small_random(p=(3, 3, 3), n=(3, 3, 3), n_ref=30, seed=9, ncomp=3),
 ])
 def test_extraction_adjoint_of_point_evaluation(make):
