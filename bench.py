@@ -132,12 +132,23 @@ def adjoint_step(dev, steps: int = 10):
         P.render(sc, wl.views, bezier=bez.detach())
     fb.record()
     torch.cuda.synchronize()
+    # adjoint of the extraction: dL/d(blocks) -> dL/d(LR coefficients)
+    g = bez.grad.detach().clone()
+    vol.extract_backward(g)
+    xa, xb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    xa.record()
+    for _ in range(steps):
+        vol.extract_backward(g)
+    xb.record()
+    torch.cuda.synchronize()
     ms = a.elapsed_time(b) / steps
     fms = fa.elapsed_time(fb) / steps
-    log("adjoint: forward+loss+backward %.3f ms (forward alone %.3f ms), %d samples per forward" % (ms, fms, samples))
+    xms = xa.elapsed_time(xb) / steps
+    log("adjoint: forward+loss+backward %.3f ms (forward alone %.3f ms), %d samples per forward; "
+        "extraction adjoint %.3f ms" % (ms, fms, samples, xms))
     return {"workload": "scalar (2,2,2), %d elements, 4 x 512^2 views, L2 loss, grad wrt Bezier blocks and table"
                         % vol.n_elem, "step_ms": ms, "forward_ms": fms, "samples_per_forward": samples,
-            "samples_per_s_fwd_bwd": samples / (ms / 1e3)}
+            "samples_per_s_fwd_bwd": samples / (ms / 1e3), "extraction_adjoint_ms": xms}
 
 
 def lookup_sweep(dev, name: str, steps: int = 10):
