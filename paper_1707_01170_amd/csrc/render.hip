@@ -1,10 +1,11 @@
 // Ray casting of LR-spline volumes on gfx950 (Sec. 4): forward render,
 // adjoint, single-ray traces and the forest look-up kernel.
 //
-// Mapping: one 64-lane wavefront renders an 8x8 pixel tile; a 256-thread
-// workgroup renders a 16x16 group (2x2 tiles); workgroups follow the groups
-// in row-major order, so the round-robin dealing of workgroups to the eight
-// XCDs spreads the uneven per-pixel work evenly over them.
+// Mapping: one workgroup of one 64-lane wavefront renders an 8x8 pixel tile;
+// workgroups follow the tiles in row-major order, so the round-robin dealing
+// of workgroups to the eight XCDs spreads the uneven per-pixel work evenly
+// over them, and single-wave workgroups let every CU refill at wave
+// granularity.
 //
 // Per lane the ray keeps its current element (box, step and Bezier block in
 // registers) and only descends the k-d forest (Alg. 1) when a sample leaves
@@ -28,8 +29,8 @@ namespace {
 using namespace lrvr;
 
 constexpr int kTile = 8;
-constexpr int kGroup = 16;            // pixels per workgroup side
-constexpr int kThreads = 256;
+constexpr int kGroup = 8;             // pixels per workgroup side (one tile)
+constexpr int kThreads = 64;
 constexpr int kMaxViews = LR_MAX_VIEWS_PER_LAUNCH;
 
 struct SceneK {
@@ -52,7 +53,7 @@ struct SceneK {
 
 struct ViewsK {
   lr_view v[kMaxViews];
-  int64_t group_base[kMaxViews + 1];   // prefix sums of 16x16 groups
+  int64_t group_base[kMaxViews + 1];   // prefix sums of 8x8 tiles
   int32_t groups_x[kMaxViews];
   int32_t n;
 };
@@ -384,9 +385,9 @@ struct TraceVisitor : Composite {
   }
 };
 
-// Workgroup b renders group b of the views' row-major group order.  The
+// Workgroup b renders tile b of the views' row-major tile order.  The
 // hardware deals consecutive workgroups to the eight XCDs in turn, so every
-// XCD gets groups from all over the image: the work per pixel is very uneven
+// XCD gets tiles from all over the image: the work per pixel is very uneven
 // (rays through dense regions take several times more samples), and handing
 // each XCD a contiguous band instead left the busiest XCD with ~1.9x the mean
 // work (and 1.65x the frame time on the 1080p vector workload).
@@ -395,9 +396,9 @@ __device__ inline bool locate(const ViewsK& vk, int64_t g, int& v, int& px, int&
   while (v + 1 < vk.n && g >= vk.group_base[v + 1]) ++v;
   const int64_t lg = g - vk.group_base[v];
   const int gx = (int)(lg % vk.groups_x[v]), gy = (int)(lg / vk.groups_x[v]);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  px = gx * kGroup + (wave & 1) * kTile + (lane & 7);
-  py = gy * kGroup + (wave >> 1) * kTile + (lane >> 3);
+  const int lane = threadIdx.x & 63;
+  px = gx * kGroup + (lane & 7);
+  py = gy * kGroup + (lane >> 3);
   return px < vk.v[v].width && py < vk.v[v].height;
 }
 
@@ -405,7 +406,7 @@ template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK, int SH>
 __global__ __launch_bounds__(kThreads) void render_kernel(const SceneK s, const ViewsK vk, float4* __restrict__ rgba,
                                                          uint32_t* __restrict__ nsamples) {
   __shared__ float4 lut[256];
-  lut[threadIdx.x] = s.lut[threadIdx.x];
+  for (int i = threadIdx.x; i < 256; i += kThreads) lut[i] = s.lut[i];
   __syncthreads();
   int v, px, py;
   if (!locate(vk, blockIdx.x, v, px, py)) return;
@@ -607,7 +608,7 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(const SceneK s, cons
   __shared__ float glut_s[1024];
   __shared__ int32_t htag[S];
   __shared__ float hval[S * NB];
-  lut[threadIdx.x] = s.lut[threadIdx.x];
+  for (int i = threadIdx.x; i < 256; i += kThreads) lut[i] = s.lut[i];
   for (int i = threadIdx.x; i < 1024; i += kThreads) glut_s[i] = 0.0f;
   for (int i = threadIdx.x; i < S; i += kThreads) htag[i] = -1;
   for (int i = threadIdx.x; i < S * NB; i += kThreads) hval[i] = 0.0f;
