@@ -28,8 +28,7 @@ namespace {
 
 using namespace lrvr;
 
-constexpr int kTile = 8;
-constexpr int kGroup = 8;             // pixels per workgroup side (one tile)
+constexpr int kGroup = 8;             // pixels per workgroup side (one 8x8 tile)
 constexpr int kThreads = 64;
 constexpr int kMaxViews = LR_MAX_VIEWS_PER_LAUNCH;
 
@@ -486,8 +485,8 @@ __global__ void lookup_octree_kernel(const uint32_t* __restrict__ root, const ui
 template <int P>
 struct GradTable {
   static constexpr int NB = (P + 1) * (P + 1) * (P + 1);
-  static constexpr int kSlots = P == 3 ? 128 : 256;   // per workgroup
-  static constexpr int kLog2Slots = P == 3 ? 7 : 8;
+  static constexpr int kSlots = 128;   // per workgroup (one 8x8 tile of rays)
+  static constexpr int kLog2Slots = 7;
   static constexpr int kProbes = 16;
 };
 
