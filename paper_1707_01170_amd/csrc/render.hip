@@ -29,6 +29,7 @@ namespace {
 using namespace lrvr;
 
 constexpr int kGroup = 8;             // pixels per workgroup side (one 8x8 tile)
+constexpr int kQuad = 2;              // workgroups per side of a block kept on one XCD
 constexpr int kThreads = 64;
 constexpr int kMaxViews = LR_MAX_VIEWS_PER_LAUNCH;
 
@@ -52,8 +53,8 @@ struct SceneK {
 
 struct ViewsK {
   lr_view v[kMaxViews];
-  int64_t group_base[kMaxViews + 1];   // prefix sums of 8x8 tiles
-  int32_t groups_x[kMaxViews];
+  int64_t quad_base[kMaxViews + 1];    // prefix sums of kQuad x kQuad blocks of tiles
+  int32_t quads_x[kMaxViews];
   int32_t n;
 };
 
@@ -384,17 +385,27 @@ struct TraceVisitor : Composite {
   }
 };
 
-// Workgroup b renders tile b of the views' row-major tile order.  The
-// hardware deals consecutive workgroups to the eight XCDs in turn, so every
-// XCD gets tiles from all over the image: the work per pixel is very uneven
-// (rays through dense regions take several times more samples), and handing
-// each XCD a contiguous band instead left the busiest XCD with ~1.9x the mean
-// work (and 1.65x the frame time on the 1080p vector workload).
-__device__ inline bool locate(const ViewsK& vk, int64_t g, int& v, int& px, int& py) {
+// Work distribution.  The hardware deals consecutive workgroups to the
+// eight XCDs in turn: workgroup b runs on XCD b mod 8.  The tiles are grouped
+// in blocks of kQuad x kQuad (row-major over each view); XCD x renders the
+// blocks x, x + 8, x + 16, ..., one workgroup per tile, so a block's rays,
+// which share elements, meet in one XCD's L2, while every XCD gets blocks
+// from all over the image.  The work per pixel is very uneven (rays through
+// dense regions take several times more samples): giving each XCD one
+// contiguous band of the image instead left the busiest XCD with ~1.9x the
+// mean work.  b -> (block, tile) is a bijection onto the blocks padded to a
+// multiple of 8; tiles outside the image do nothing.
+__device__ inline bool locate(const ViewsK& vk, int64_t b, int& v, int& px, int& py) {
+  constexpr int QQ = kQuad * kQuad;
+  const int64_t k = b >> 3;
+  const int64_t q = (b & 7) + 8 * (k / QQ);
+  const int w = (int)(k % QQ);
   v = 0;
-  while (v + 1 < vk.n && g >= vk.group_base[v + 1]) ++v;
-  const int64_t lg = g - vk.group_base[v];
-  const int gx = (int)(lg % vk.groups_x[v]), gy = (int)(lg / vk.groups_x[v]);
+  if (q >= vk.quad_base[vk.n]) return false;
+  while (v + 1 < vk.n && q >= vk.quad_base[v + 1]) ++v;
+  const int64_t lq = q - vk.quad_base[v];
+  const int gx = (int)(lq % vk.quads_x[v]) * kQuad + w % kQuad;
+  const int gy = (int)(lq / vk.quads_x[v]) * kQuad + w / kQuad;
   const int lane = threadIdx.x & 63;
   px = gx * kGroup + (lane & 7);
   py = gy * kGroup + (lane >> 3);
@@ -725,14 +736,14 @@ lr_status check_view(const lr_view& v) {
 int64_t pack_views(const lr_view* views, int32_t n, ViewsK& vk) {
   std::memset(&vk, 0, sizeof vk);
   vk.n = n;
-  vk.group_base[0] = 0;
+  vk.quad_base[0] = 0;
   for (int i = 0; i < n; ++i) {
     vk.v[i] = views[i];
-    vk.groups_x[i] = (views[i].width + kGroup - 1) / kGroup;
-    const int64_t gy = (views[i].height + kGroup - 1) / kGroup;
-    vk.group_base[i + 1] = vk.group_base[i] + (int64_t)vk.groups_x[i] * gy;
+    const int64_t gx = (views[i].width + kGroup - 1) / kGroup, gy = (views[i].height + kGroup - 1) / kGroup;
+    vk.quads_x[i] = (int32_t)((gx + kQuad - 1) / kQuad);
+    vk.quad_base[i + 1] = vk.quad_base[i] + (int64_t)vk.quads_x[i] * ((gy + kQuad - 1) / kQuad);
   }
-  return vk.group_base[n];
+  return 8 * ((vk.quad_base[n] + 7) / 8) * (int64_t)kQuad * kQuad;   // workgroups to launch
 }
 
 template <int P, int NCOMP, typename CT, int MODE, int COLOR>
