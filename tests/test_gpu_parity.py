@@ -150,11 +150,12 @@ def test_small_full_images(name, w, h):
     assert np.all(ns <= rns) and np.mean(ns == rns) > 0.5
 
 
-@pytest.mark.parametrize("name", ["blobs50k", "vortex200k", "scalar20k"])
-def test_full_size_sampled(name):
-    """The full-size launch (as benchmarked), checked on seeded pixels and one tile."""
-    say("[gpu] full size", name)
-    wl, sc = scene(name)
+@pytest.mark.parametrize("name,blocks", [("blobs50k", 128), ("vortex200k", 256), ("scalar20k", 128)])
+def test_full_size_sampled(name, blocks):
+    """The full-size launch in the benchmark's configuration (forest size as
+    timed), checked on seeded pixels and one tile."""
+    say("[gpu] full size", name, blocks)
+    wl, sc = scene(name, blocks=blocks)
     rgba, offs, ns = _render(sc, wl.views)
     v = len(wl.views) - 1
     view = wl.views[v]
