@@ -145,21 +145,13 @@ __device__ inline TF transfer(const float4* lut, float v, float vmin, float inv_
 }
 
 // RGB of hue h in [0,1) at full saturation and value.
+// (The hexcone's six sectors written as clamped distances from the sector
+// centres of each primary: branch-free.)
 __device__ inline void hsv_full(float h, float rgb[3]) {
   const float h6 = h * 6.0f;
-  const float k = floorf(h6);
-  const float f = h6 - k;
-  int s = (int)k;
-  s = s >= 6 ? 0 : s;
-  const float q = 1.0f - f;
-  switch (s) {
-    case 0: rgb[0] = 1.0f; rgb[1] = f; rgb[2] = 0.0f; break;
-    case 1: rgb[0] = q; rgb[1] = 1.0f; rgb[2] = 0.0f; break;
-    case 2: rgb[0] = 0.0f; rgb[1] = 1.0f; rgb[2] = f; break;
-    case 3: rgb[0] = 0.0f; rgb[1] = q; rgb[2] = 1.0f; break;
-    case 4: rgb[0] = f; rgb[1] = 0.0f; rgb[2] = 1.0f; break;
-    default: rgb[0] = 1.0f; rgb[1] = 0.0f; rgb[2] = q; break;
-  }
+  rgb[0] = fminf(fmaxf(fabsf(h6 - 3.0f) - 1.0f, 0.0f), 1.0f);
+  rgb[1] = fminf(fmaxf(2.0f - fabsf(h6 - 2.0f), 0.0f), 1.0f);
+  rgb[2] = fminf(fmaxf(2.0f - fabsf(h6 - 4.0f), 0.0f), 1.0f);
 }
 
 // atan(t) for t in [0, 1] as t * P(t^2), degree 15, coefficients fitted by
@@ -254,7 +246,9 @@ __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, V
     }
     float p[3];
     position(r, ts, p);
-    if (!inside(p, lo, hi)) {
+    // Half-open containment; hi is stored as 2 where the box is closed at 1
+    // (positions are clamped to [0,1]), so one comparison per bound suffices.
+    if (!(lo[0] <= p[0] && p[0] < hi[0] && lo[1] <= p[1] && p[1] < hi[1] && lo[2] <= p[2] && p[2] < hi[2])) {
       e = find_element<LK>(s, p);
       const float2* b2 = reinterpret_cast<const float2*>(s.box + 6 * (int64_t)e);
       const float2 b01 = b2[0], b23 = b2[1], b45 = b2[2];
@@ -263,6 +257,7 @@ __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, V
       const float side = fminf(fminf(hi[0] - lo[0], hi[1] - lo[1]), hi[2] - lo[2]);
       ds_e = side * step_scale;
       for (int a = 0; a < 3; ++a) inv[a] = __builtin_amdgcn_rcpf(hi[a] - lo[a]);
+      for (int a = 0; a < 3; ++a) hi[a] = hi[a] == 1.0f ? 2.0f : hi[a];
       Coef<NCF, CT>::load(s.bez, s.stride, e, c);
     }
     Sample<P> sm;
