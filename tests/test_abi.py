@@ -371,3 +371,24 @@ def test_streamlines_validate_first():
     assert st(s16, prm()) == L.LR_EINVAL
     sb = _scene_struct(ncomp=3, color_mode=L.LR_COLOR_HUE, blocks=(3, 4, 4))
     assert st(sb, prm()) == L.LR_ENOTPOW2
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/lrvr.h compiles as C99 and its struct sizes and offsets match the binding's."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "h.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lrvr.h"\n'
+                   'int main(void) { printf("%d %d %d %d %d %d %d %d\\n", (int)sizeof(lr_scene), (int)sizeof(lr_view), '
+                   '(int)sizeof(lr_lrspline), (int)sizeof(lr_kdnode), (int)sizeof(lr_forest_stats), '
+                   '(int)sizeof(lr_stream_params), (int)offsetof(lr_scene, shading), (int)offsetof(lr_scene, lookup));'
+                   ' return 0; }\n')
+    exe = tmp_path / "h"
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-pedantic", "-I", os.path.join(ROOT, "include"),
+                           str(src), "-o", str(exe)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    want = [ctypes.sizeof(L.SceneC), ctypes.sizeof(L.ViewC), ctypes.sizeof(L.LRSplineDev), ctypes.sizeof(L.KdNode),
+            ctypes.sizeof(L.ForestStats), ctypes.sizeof(L.StreamParams), L.SceneC.shading.offset, L.SceneC.lookup.offset]
+    assert got == want
