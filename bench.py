@@ -358,6 +358,24 @@ def main():
     times = np.array([a.elapsed_time(b) for a, b in ev])      # ms, per launch, on the launch stream
     log("frame ms: mean %.3f p50 %.3f p99 %.3f; wall %.3f s" % (times.mean(), np.percentile(times, 50),
                                                                np.percentile(times, 99), wall))
+    # FP16 Bezier storage with FP32 arithmetic: the same frame
+    vol16 = P.Volume(wl.spline, blocks=args.blocks, dtype="f16", device=dev)
+    sc16 = P.Scene(vol16, P.RenderParams.of(wl))
+    out16 = torch.empty_like(rgba)
+    for _ in range(2):
+        P.render(sc16, views, out=out16)
+    ha, hb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ha.record(stream)
+    for _ in range(args.steps):
+        P.render(sc16, views, out=out16)
+    hb.record(stream)
+    torch.cuda.synchronize()
+    f16_ms = ha.elapsed_time(hb) / args.steps
+    f16_diff = float((out16 - rgba).abs().max() / rgba.abs().max())
+    log("FP16 blocks: %.3f ms per frame (%.2fx), peak-relative difference to FP32 %.2e" % (f16_ms, times.mean() / f16_ms, f16_diff))
+    fp16 = {"storage": "FP16 Bezier blocks, FP32 arithmetic", "ms_per_frame": f16_ms,
+            "samples_per_s": samples / (f16_ms / 1e3), "peak_rel_diff_vs_f32": f16_diff}
+    del vol16, sc16, out16
     # local illumination (Sec. 4.1): the same frame with a head light
     import dataclasses
     sc_lit = P.Scene(vol, dataclasses.replace(P.RenderParams.of(wl), shading="headlight"))
@@ -420,6 +438,7 @@ def main():
         "serving": serving,
         "adjoint": adjoint,
         "illumination": illumination,
+        "fp16_storage": fp16,
         "streamlines": lines,
     }
     if sweep is not None:
