@@ -59,12 +59,17 @@ __device__ inline int32_t octree_lookup(const uint32_t* __restrict__ root, const
 }
 
 // ---------------------------------------------------------------- Bezier blocks
+// A lane's copy of one element's block: Reg is the register type, get(c, j)
+// the coefficient j as an FP32 value.  FP16 blocks stay packed two to a
+// register and are widened inside the multiply-add (the conversion is exact).
 template <int NCF, typename CT>
 struct Coef;
 
 template <int NCF>
 struct Coef<NCF, float> {
+  using Reg = float;
   static constexpr int N4 = (NCF + 3) / 4;
+  static constexpr int kRegs = 4 * N4;
   __device__ static inline void load(const void* bez, int64_t stride, int32_t e, float* c) {
     const float4* r4 = reinterpret_cast<const float4*>(static_cast<const float*>(bez) + (int64_t)e * stride);
 #pragma unroll
@@ -76,30 +81,32 @@ struct Coef<NCF, float> {
       c[4 * i + 3] = v.w;
     }
   }
-  static constexpr int kRegs = 4 * N4;
+  __device__ static inline float get(const float* c, int j) { return c[j]; }
 };
 
 template <int NCF>
 struct Coef<NCF, _Float16> {
+  using Reg = uint32_t;
   static constexpr int N8 = (NCF + 7) / 8;
-  __device__ static inline void load(const void* bez, int64_t stride, int32_t e, float* c) {
+  static constexpr int kRegs = 4 * N8;     // two coefficients per register
+  __device__ static inline void load(const void* bez, int64_t stride, int32_t e, uint32_t* c) {
     const uint4* r8 = reinterpret_cast<const uint4*>(static_cast<const _Float16*>(bez) + (int64_t)e * stride);
 #pragma unroll
     for (int i = 0; i < N8; ++i) {
       const uint4 v = r8[i];
-      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        _Float16 lo, hi;
-        const unsigned short l = (unsigned short)(w[k] & 0xffffu), h = (unsigned short)(w[k] >> 16);
-        memcpy(&lo, &l, 2);
-        memcpy(&hi, &h, 2);
-        c[8 * i + 2 * k] = (float)lo;
-        c[8 * i + 2 * k + 1] = (float)hi;
-      }
+      c[4 * i + 0] = v.x;
+      c[4 * i + 1] = v.y;
+      c[4 * i + 2] = v.z;
+      c[4 * i + 3] = v.w;
     }
   }
-  static constexpr int kRegs = 8 * N8;
+  __device__ static inline float get(const uint32_t* c, int j) {
+    const uint32_t w = c[j >> 1];
+    const unsigned short bits = (j & 1) ? (unsigned short)(w >> 16) : (unsigned short)(w & 0xffffu);
+    _Float16 h;
+    memcpy(&h, &bits, 2);
+    return (float)h;
+  }
 };
 
 template <int P>
@@ -121,9 +128,10 @@ __device__ inline void bernstein(float u, float b[P + 1]) {
   }
 }
 
-// sum_j c[j] Bx[jx] By[jy] Bz[jz] for one component (x fastest).
-template <int P>
-__device__ inline float contract(const float* c, const float* bx, const float* by, const float* bz) {
+// sum_j c[base + j] Bx[jx] By[jy] Bz[jz] for one component (x fastest).
+template <int P, class CF>
+__device__ inline float contract(const typename CF::Reg* c, int base, const float* bx, const float* by,
+                                 const float* bz) {
   constexpr int Q = P + 1;
   float acc = 0.0f;
 #pragma unroll
@@ -133,7 +141,7 @@ __device__ inline float contract(const float* c, const float* bx, const float* b
     for (int jy = 0; jy < Q; ++jy) {
       float ax = 0.0f;
 #pragma unroll
-      for (int ix = 0; ix < Q; ++ix) ax = fmaf(c[(kz * Q + jy) * Q + ix], bx[ix], ax);
+      for (int ix = 0; ix < Q; ++ix) ax = fmaf(CF::get(c, base + (kz * Q + jy) * Q + ix), bx[ix], ax);
       ay = fmaf(ax, by[jy], ay);
     }
     acc = fmaf(ay, bz[kz], acc);
@@ -172,9 +180,10 @@ __device__ inline void bernstein_d(float u, float b[P + 1], float db[P + 1]) {
 
 // Value and local-coordinate gradient (d/du, d/dv, d/dw) of one component,
 // sharing the partial sums: out = {f, f_u, f_v, f_w}.
-template <int P>
-__device__ inline void contract_grad(const float* c, const float* bx, const float* by, const float* bz,
-                                     const float* dx, const float* dy, const float* dz, float out[4]) {
+template <int P, class CF>
+__device__ inline void contract_grad(const typename CF::Reg* c, int base, const float* bx, const float* by,
+                                     const float* bz, const float* dx, const float* dy, const float* dz,
+                                     float out[4]) {
   constexpr int Q = P + 1;
   float f = 0.0f, fu = 0.0f, fv = 0.0f, fw = 0.0f;
 #pragma unroll
@@ -185,7 +194,7 @@ __device__ inline void contract_grad(const float* c, const float* bx, const floa
       float ax = 0.0f, axu = 0.0f;
 #pragma unroll
       for (int ix = 0; ix < Q; ++ix) {
-        const float cv = c[(kz * Q + jy) * Q + ix];
+        const float cv = CF::get(c, base + (kz * Q + jy) * Q + ix);
         ax = fmaf(cv, bx[ix], ax);
         axu = fmaf(cv, dx[ix], axu);
       }

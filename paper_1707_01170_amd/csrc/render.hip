@@ -227,7 +227,8 @@ template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK = LR_LOOKUP
 __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, Visitor& vis) {
   constexpr int NB = (P + 1) * (P + 1) * (P + 1);
   constexpr int NCF = NCOMP * NB;
-  float c[Coef<NCF, CT>::kRegs];
+  using CF = Coef<NCF, CT>;
+  typename CF::Reg c[CF::kRegs];
   float lo[3] = {2.0f, 2.0f, 2.0f}, hi[3] = {-1.0f, -1.0f, -1.0f}, inv[3] = {0.0f, 0.0f, 0.0f};
   float ds_e = 0.0f;
   int32_t e = -1;
@@ -285,7 +286,7 @@ __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, V
 #pragma unroll
       for (int q = 0; q < NCOMP; ++q) {
         float o[4];
-        contract_grad<P>(c + q * NB, sm.bx, sm.by, sm.bz, dx, dy, dz, o);
+        contract_grad<P, CF>(c, q * NB, sm.bx, sm.by, sm.bz, dx, dy, dz, o);
         f[q] = o[0];
         const float w = NCOMP == 1 ? 1.0f : o[0];      // grad |f| is parallel to sum_q f_q grad f_q
 #pragma unroll
@@ -312,9 +313,9 @@ __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, V
       bernstein<P>(ux, sm.bx);
       bernstein<P>(uy, sm.by);
       bernstein<P>(uz, sm.bz);
-      const float fx = contract<P>(c, sm.bx, sm.by, sm.bz);
-      const float fy = contract<P>(c + NB, sm.bx, sm.by, sm.bz);
-      const float fz = contract<P>(c + 2 * NB, sm.bx, sm.by, sm.bz);
+      const float fx = contract<P, CF>(c, 0, sm.bx, sm.by, sm.bz);
+      const float fy = contract<P, CF>(c, NB, sm.bx, sm.by, sm.bz);
+      const float fz = contract<P, CF>(c, 2 * NB, sm.bx, sm.by, sm.bz);
       const float vm = __builtin_amdgcn_sqrtf(fmaf(fx, fx, fmaf(fy, fy, fz * fz)));
       sm.tf = transfer(lut, vm, s.vmin, s.inv_range);
       hsv_full(hue_of(fx, fy), sm.csrc);
@@ -322,7 +323,7 @@ __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, V
       bernstein<P>(ux, sm.bx);
       bernstein<P>(uy, sm.by);
       bernstein<P>(uz, sm.bz);
-      const float v = contract<P>(c, sm.bx, sm.by, sm.bz);
+      const float v = contract<P, CF>(c, 0, sm.bx, sm.by, sm.bz);
       sm.tf = transfer(lut, v, s.vmin, s.inv_range);
       sm.csrc[0] = sm.tf.rgba.x;
       sm.csrc[1] = sm.tf.rgba.y;

@@ -154,7 +154,7 @@ struct Field {
     bernstein<P>(fminf(fmaxf((p[1] - lo[1]) * inv[1], 0.0f), 1.0f), by);
     bernstein<P>(fminf(fmaxf((p[2] - lo[2]) * inv[2], 0.0f), 1.0f), bz);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) f[q] = (R)contract<P>(c + q * NB, bx, by, bz);
+    for (int q = 0; q < 3; ++q) f[q] = (R)contract<P, Coef<3 * NB, float>>(c, q * NB, bx, by, bz);
   }
 };
 
