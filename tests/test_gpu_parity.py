@@ -232,3 +232,25 @@ def test_bad_input_is_rejected():
     ok, _, _ = P.render(sc, [resized(wl.views[0], 8, 8)])
     torch.cuda.synchronize()
     assert torch.isfinite(ok).all()
+
+
+def test_serving_configuration_full_size_fp16():
+    """The serving configuration at its largest request size: the blob volume
+    with FP16 blocks (forest 128^3), one 2048^2 view, checked on seeded pixels
+    and one tile against the oracle; the FP32 blocks on the same pixels for
+    comparison."""
+    import lrgen
+    from gpu_util import TOL_F16
+    say("[gpu] serving configuration, 2048^2, FP16")
+    wl16, sc16 = scene("blobs50k", blocks=128, dtype="f16")
+    _, sc32 = scene("blobs50k", blocks=128)
+    view = lrgen.blob_requests(n=64)[0].view
+    view = resized(view, 2048, 2048)
+    a, _, _ = _render(sc16, [view])
+    b, _, _ = _render(sc32, [view])
+    ii, jj = sample_pixels(view, 1024, seed=6, tile=24)
+    ref, _, _ = oracle_render("blobs50k", view, ii, jj)
+    e16, r16 = peak_rel(a[jj * view.width + ii], ref)
+    e32, r32 = peak_rel(b[jj * view.width + ii], ref)
+    say("serving config 2048^2: fp16 peak-rel %.3e rms %.3e | fp32 %.3e rms %.3e" % (e16, r16, e32, r32))
+    assert e16 <= TOL_F16 and e32 <= TOL_F32
