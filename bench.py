@@ -32,18 +32,34 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ("render.hip", "eval.h", "common.h")
+
+
+def kernel_digest() -> str:
+    """SHA-1 of the render kernel's code (its sources with comments and
+    whitespace removed), so that the counters stay attached to the code they
+    were taken on."""
+    import hashlib
+    import re
+    h = hashlib.sha1()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1707_01170_amd", "csrc", name)) as f:
+            code = re.sub(r"/\*.*?\*/", " ", f.read(), flags=re.S)
+        code = re.sub(r"//[^\n]*", " ", code)
+        h.update(" ".join(code.split()).encode())
+    return h.hexdigest()
+
+
 def measured_traffic(blocks: int):
     """HBM bytes per render launch from the committed counter summary, or None
-    if the render source changed since the counters were taken."""
-    import hashlib
+    if the render kernel's code changed since the counters were taken."""
     try:
         with open(os.path.join(ROOT, "profiles", "render_kernel_vector1080p_traffic.json")) as f:
             rec = json.load(f)
-        with open(os.path.join(ROOT, "paper_1707_01170_amd", "csrc", "render.hip"), "rb") as f:
-            src = hashlib.sha1(f.read()).hexdigest()
+        src = kernel_digest()
     except (OSError, ValueError):
         return None
-    if rec.get("source_sha1") != src or rec.get("forest_blocks") != blocks:
+    if rec.get("kernel_code_sha1") != src or rec.get("forest_blocks") != blocks:
         return None
     return float(rec["traffic_bytes_per_launch"])
 
@@ -303,7 +319,7 @@ def main():
                     help="requests of the serving stream on the blob volume with FP16 blocks (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only (--gpus 1); multi-GPU runs are not part of this build",
+        print("bench.py measures one GPU only (--gpus 1): the renderer has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
 

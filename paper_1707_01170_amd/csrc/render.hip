@@ -2,10 +2,9 @@
 // adjoint, single-ray traces and the forest look-up kernel.
 //
 // Mapping: one workgroup of one 64-lane wavefront renders an 8x8 pixel tile;
-// workgroups follow the tiles in row-major order, so the round-robin dealing
-// of workgroups to the eight XCDs spreads the uneven per-pixel work evenly
-// over them, and single-wave workgroups let every CU refill at wave
-// granularity.
+// 2x2 blocks of tiles are dealt to the eight XCDs in turn (see locate), which
+// spreads the uneven per-pixel work evenly over them, and single-wave
+// workgroups let every CU refill at wave granularity.
 //
 // Per lane the ray keeps its current element (box, step and Bezier block in
 // registers) and only descends the k-d forest (Alg. 1) when a sample leaves

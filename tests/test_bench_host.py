@@ -1,0 +1,72 @@
+"""Host-side pieces of the benchmark: the algorithmic operation count it
+prices the render kernel with, the code digest that keeps the committed HBM
+counters attached to the kernel code they were taken on, and the refusal of
+multi-GPU runs."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_flops_per_sample_counts():
+    # (2,2,2) vector field: 6 + 6 + 15 + 2*(27+9+3)*3 + 11 + 13 + 13
+    assert bench.flops_per_sample(2, 3) == 298
+    # (2,2,2) scalar and (3,3,3) scalar
+    assert bench.flops_per_sample(2, 1) == 6 + 6 + 15 + 78 + 11 + 13
+    assert bench.flops_per_sample(3, 1) == 6 + 6 + 30 + 2 * (64 + 16 + 4) + 11 + 13
+
+
+def _copy_sources(dst):
+    d = os.path.join(dst, "paper_1707_01170_amd", "csrc")
+    os.makedirs(d)
+    for name in bench.KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1707_01170_amd", "csrc", name)) as f, \
+                open(os.path.join(d, name), "w") as g:
+            g.write(f.read())
+    return d
+
+
+def test_kernel_digest_ignores_comments_not_code(tmp_path, monkeypatch):
+    d = _copy_sources(str(tmp_path))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    base = bench.kernel_digest()
+    p = os.path.join(d, "render.hip")
+    src = open(p).read()
+    open(p, "w").write("// a new comment\n/* and a\n block one */\n" + src.replace("\n", "\n\n", 3))
+    assert bench.kernel_digest() == base
+    open(p, "w").write(src.replace("kQuad = 2", "kQuad = 4", 1))
+    assert bench.kernel_digest() != base
+    open(p, "w").write(src)
+    q = os.path.join(d, "eval.h")
+    ev = open(q).read()
+    open(q, "w").write(ev + "\nconstexpr int kUnused = 1;\n")
+    assert bench.kernel_digest() != base
+
+
+def test_measured_traffic_tracks_the_code(tmp_path, monkeypatch):
+    import shutil
+    d = _copy_sources(str(tmp_path))
+    os.makedirs(os.path.join(str(tmp_path), "profiles"))
+    shutil.copy(os.path.join(ROOT, "profiles", "render_kernel_vector1080p_traffic.json"),
+                os.path.join(str(tmp_path), "profiles"))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    t = bench.measured_traffic(256)
+    if t is None:
+        pytest.skip("the render kernel changed since its counters were taken")
+    assert t > 0 and bench.measured_traffic(128) is None
+    p = os.path.join(d, "render.hip")
+    open(p, "a").write("\nstatic int changed_code;\n")
+    assert bench.measured_traffic(256) is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
