@@ -481,7 +481,7 @@ __global__ void lookup_octree_kernel(const uint32_t* __restrict__ root, const ui
 //
 // Accumulation: a lane sums the gradient of consecutive samples of one
 // element in registers; on element change it adds the sum into a workgroup
-// hash table in LDS (the rays of a 16x16 pixel group share most elements):
+// hash table in LDS (the 64 rays of an 8x8 tile share most elements):
 // a slot is claimed for an element by compare-and-swap on its tag (linear
 // probing), values are added with LDS atomics, and the table is written to
 // global memory with atomics once, when the workgroup ends (if it fills, the
