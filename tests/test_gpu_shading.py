@@ -8,7 +8,7 @@ import pytest
 import torch
 
 from conftest import workload
-from gpu_util import TOL_F32, oracle_parts, peak_rel, resized, say, scene
+from gpu_util import TOL_F32, oracle_parts, peak_rel, resized, sample_pixels, say, scene
 
 pytestmark = pytest.mark.gpu
 
@@ -80,3 +80,24 @@ def test_linear_field_constant_intensity():
     plain, lit = plain.cpu().numpy(), lit.cpu().numpy()
     assert np.array_equal(plain[:, 3], lit[:, 3])
     assert np.abs(lit[:, :3] - I * plain[:, :3]).max() <= 1e-5 * np.abs(plain).max()
+
+
+def test_full_size_sampled_headlight():
+    """The illuminated 1080p launch as the benchmark times it (vector volume,
+    forest 256^3, headlight), checked on seeded pixels and one tile."""
+    import paper_1707_01170_amd as P
+    say("[gpu] shading full size")
+    name = "vortex200k"
+    wl, sc = scene(name, blocks=256)
+    view = wl.views[0]
+    prm = dataclasses.replace(P.RenderParams.of(wl), shading="headlight")
+    rgba, _, ns = P.render(P.Scene(sc.volume, prm), [view], nsamples=True)
+    torch.cuda.synchronize()
+    ii, jj = sample_pixels(view, 1024, seed=9, tile=24)
+    k = jj * view.width + ii
+    ref, rns, _ = _oracle(name, view, "headlight", (0.0, 0.0, 1.0), ii=ii, jj=jj)
+    got = rgba.cpu().numpy()[k]
+    err, rms = peak_rel(got, ref)
+    say("headlight 1080p sampled: peak-rel %.3e rms %.3e" % (err, rms))
+    assert np.array_equal(ns.cpu().numpy()[k] > 0, rns > 0)
+    assert err <= TOL_F32

@@ -154,3 +154,34 @@ def test_stopping_rules_on_the_gpu():
     assert np.all(np.abs(tim[np.arange(10), cnt - 1] - 0.01) <= 1e-17)
     pts, tim, cnt = _gpu_lines(seeds, method="rk2", base=1.0, t_end=3.0, max_samples=5)
     assert np.all(cnt == 5)
+
+
+def test_bench_configuration_sampled():
+    """The launch the benchmark times (16 384 seeds, RK4 with the Eq. 4
+    step, mixed precision, t_end 1, at most 2048 points), checked on a
+    spread of its lines against the oracle as in the heuristic test."""
+    import os
+    import sys
+    from oracle import streamline as ost
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    say("[gpu] streamline bench configuration")
+    wl = workload(NAME)
+    seeds = bench._stream_seeds(16384)
+    kw = dict(method="rk4", step="heuristic", precision="mixed", base=1.0, t_end=1.0, max_samples=2048)
+    pts, tim, cnt = _gpu_lines(seeds, **kw)
+    pick = np.linspace(0, len(seeds) - 1, 16).astype(np.int64)
+    X, T, c = ost.integrate(_field(), seeds[pick], "rk4", "heuristic", 1.0, 1.0, 2048,
+                            elem_box=wl.spline.elem_box, eidx=oracle_parts(NAME)[1], p_max=2)
+    same = 0
+    for n_, j in enumerate(pick):
+        n = min(cnt[j], c[n_])
+        d = tim[j, :n] != T[n_, :n]
+        k = int(np.argmax(d)) if np.any(d) else n
+        assert k >= 2
+        assert np.abs(pts[j, :k, :3] - X[n_, :k]).max() <= 1e-5
+        same += (k == n and cnt[j] == c[n_])
+    say("bench configuration: %d of %d sampled lines identical, %d..%d points over all lines" % (
+        same, len(pick), cnt.min(), cnt.max()))
+    assert same >= 0.75 * len(pick)
+    assert np.all(cnt >= 2) and cnt.max() <= 2048
