@@ -407,10 +407,21 @@ __device__ inline bool locate(const ViewsK& vk, int64_t b, int& v, int& px, int&
   return px < vk.v[v].width && py < vk.v[v].height;
 }
 
+// Occupancy of the FP16 vector and degree-3 kernels.  Their registers would
+// let 6 waves share a SIMD; at 4, compiled for 4, they run 8-12 % faster.  The
+// transfer-table array is padded to 10 KB, so a CU's 160 KB of LDS hold 16
+// single-wave workgroups and the compiler sees that bound.  (Reserving the
+// same LDS only at launch gives the occupancy without the gain.)  The other
+// kernels are limited by their registers or run fastest at full occupancy.
+template <int P, int NCOMP, typename CT>
+constexpr int lut_rows() {
+  return (sizeof(CT) == 2 && (P == 3 || NCOMP == 3)) ? (160 * 1024 / 16) / (int)sizeof(float4) : 256;
+}
+
 template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK, int SH>
 __global__ __launch_bounds__(kThreads) void render_kernel(const SceneK s, const ViewsK vk, float4* __restrict__ rgba,
                                                          uint32_t* __restrict__ nsamples) {
-  __shared__ float4 lut[256];
+  __shared__ float4 lut[lut_rows<P, NCOMP, CT>()];   // rows beyond 256 are reserved, never touched
   for (int i = threadIdx.x; i < 256; i += kThreads) lut[i] = s.lut[i];
   __syncthreads();
   int v, px, py;
