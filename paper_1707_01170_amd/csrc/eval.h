@@ -109,6 +109,37 @@ struct Coef<NCF, _Float16> {
   }
 };
 
+// FP16 storage widened to FP32 registers when the block is loaded: twice the
+// registers of the packed form, plain FP32 multiply-adds in the contraction.
+// Used where the register count is capped anyway (the illuminated vector
+// kernel), and there faster than widening inside every multiply-add.
+struct F16Widened {};
+
+template <int NCF>
+struct Coef<NCF, F16Widened> {
+  using Reg = float;
+  static constexpr int N8 = (NCF + 7) / 8;
+  static constexpr int kRegs = 8 * N8;
+  __device__ static inline void load(const void* bez, int64_t stride, int32_t e, float* c) {
+    const uint4* r8 = reinterpret_cast<const uint4*>(static_cast<const _Float16*>(bez) + (int64_t)e * stride);
+#pragma unroll
+    for (int i = 0; i < N8; ++i) {
+      const uint4 v = r8[i];
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const unsigned short lo = (unsigned short)(w[k] & 0xffffu), hi = (unsigned short)(w[k] >> 16);
+        _Float16 a, b;
+        memcpy(&a, &lo, 2);
+        memcpy(&b, &hi, 2);
+        c[8 * i + 2 * k] = (float)a;
+        c[8 * i + 2 * k + 1] = (float)b;
+      }
+    }
+  }
+  __device__ static inline float get(const float* c, int j) { return c[j]; }
+};
+
 template <int P>
 __device__ inline void bernstein(float u, float b[P + 1]) {
   const float v = 1.0f - u;

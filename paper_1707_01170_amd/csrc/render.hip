@@ -447,14 +447,19 @@ __global__ __launch_bounds__(kThreads) void render_kernel(const SceneK s, const 
 // The illuminated degree-2 vector kernel keeps the block, the value and three
 // derivatives of each component live: 173-175 VGPRs, 2 waves per SIMD.
 // Compiled for 3 waves (168 VGPRs, at most 16 bytes spilled) it runs ~10 %
-// faster (FP32 blocks; ~3 % with FP16).  The degree-3 vector kernel would
-// spill most of its block at 3 waves and keeps the plain wrapper.
-template <typename CT, int MODE>
+// faster.  With the registers capped, FP16 blocks are widened to FP32 when
+// loaded (F16Widened: 1.89 -> 1.68 ms per 1080p frame against widening in
+// every multiply-add).  The degree-3 vector kernel would spill most of its
+// block at 3 waves and keeps the plain wrapper.
+template <typename CT> struct LitStorage { using type = CT; };
+template <> struct LitStorage<_Float16> { using type = F16Widened; };
+
+template <typename CS, int MODE>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
 void render_lit_vector2_kernel(const SceneK s, const ViewsK vk, float4* __restrict__ rgba,
                                uint32_t* __restrict__ nsamples) {
   __shared__ float4 lut[256];
-  render_tile<2, 3, CT, MODE, LR_COLOR_HUE, LR_LOOKUP_FOREST, 1>(s, vk, rgba, nsamples, lut);
+  render_tile<2, 3, CS, MODE, LR_COLOR_HUE, LR_LOOKUP_FOREST, 1>(s, vk, rgba, nsamples, lut);
 }
 
 template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK, int SH>
@@ -777,8 +782,8 @@ void launch_render(const SceneK& s, const ViewsK& vk, int64_t nblk, float* rgba,
   float4* out = reinterpret_cast<float4*>(rgba);
   if (s.shading != LR_SHADE_NONE) {
     if constexpr (P == 2 && NCOMP == 3)
-      hipLaunchKernelGGL((render_lit_vector2_kernel<CT, MODE>), dim3((unsigned)nblk), dim3(kThreads), 0, st, s, vk,
-                         out, ns);
+      hipLaunchKernelGGL((render_lit_vector2_kernel<typename LitStorage<CT>::type, MODE>), dim3((unsigned)nblk),
+                         dim3(kThreads), 0, st, s, vk, out, ns);
     else
       hipLaunchKernelGGL((render_kernel<P, NCOMP, CT, MODE, COLOR, LR_LOOKUP_FOREST, 1>), dim3((unsigned)nblk),
                          dim3(kThreads), 0, st, s, vk, out, ns);
