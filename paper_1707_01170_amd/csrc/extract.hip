@@ -18,6 +18,7 @@
 namespace {
 
 constexpr int kLanes = 64;
+constexpr int64_t kExtractGrid = 8192;   // wavefronts of the forward (grid-stride over elements)
 
 struct ExtractArgs {
   int32_t p[3];
@@ -55,38 +56,72 @@ __device__ inline double dunkey(unsigned long long k) {
 }
 
 // Bernstein coefficients beta[0..p] of the B-spline with local knots
-// u[0..p+1] on [a, b]; false if [a, b] is not inside one non-empty knot span.
-__device__ bool bezier_1d(const double* u, int p, double a, double b, double* beta) {
-  int s = -1;
-  for (int q = 0; q <= p; ++q)
-    if (u[q] < u[q + 1] && u[q] <= a && b <= u[q + 1]) {
-      s = q;
-      break;
-    }
-  if (s < 0) return false;
-  // Padded knot vector T[R] = u[clamp(R - p, 0, p + 1)]; the B-spline is basis
-  // function p of T and the span [u_s, u_s+1] is span k = s + p of T.
-  const int k = s + p;
+// u[0..p+1] on [a, b], which must lie inside the non-empty knot span
+// [u_S, u_S+1].  Padded knot vector T[R] = u[clamp(R - p, 0, p + 1)]; the
+// B-spline is basis function p of T and the span is span k = S + p of T.
+// Degree and span are template parameters, so the recurrence is unrolled,
+// the knots stay in registers and divisions repeated across j are computed
+// once (the arithmetic of every value is unchanged).
+template <int P, int S>
+__device__ inline void bezier_span(const double (&u)[P + 2], double a, double b, double* beta) {
+  constexpr int k = S + P;
   auto T = [&](int R) {
-    int i = R - p;
-    i = i < 0 ? 0 : (i > p + 1 ? p + 1 : i);
+    int i = R - P;
+    i = i < 0 ? 0 : (i > P + 1 ? P + 1 : i);
     return u[i];
   };
-  for (int j = 0; j <= p; ++j) {
-    double d[4];
-    for (int r = 0; r <= p; ++r) d[r] = (k - p + r == p) ? 1.0 : 0.0;
-    for (int l = 1; l <= p; ++l) {
-      const double x = (l <= p - j) ? a : b;
-      for (int r = p; r >= l; --r) {
-        const int R = k - p + r;
+#pragma unroll
+  for (int j = 0; j <= P; ++j) {
+    double d[P + 1];
+#pragma unroll
+    for (int r = 0; r <= P; ++r) d[r] = (k - P + r == P) ? 1.0 : 0.0;
+#pragma unroll
+    for (int l = 1; l <= P; ++l) {
+      const double x = (l <= P - j) ? a : b;
+#pragma unroll
+      for (int r = P; r >= l; --r) {
+        const int R = k - P + r;
         const double tr = T(R);
-        const double al = (x - tr) / (T(R + p + 1 - l) - tr);
+        const double al = (x - tr) / (T(R + P + 1 - l) - tr);
         d[r] = (1.0 - al) * d[r - 1] + al * d[r];
       }
     }
-    beta[j] = d[p];
+    beta[j] = d[P];
   }
-  return true;
+}
+
+// The first span S of u that is non-empty and contains [a, b].
+template <int P, int S = 0>
+__device__ inline bool bezier_spans(const double (&u)[P + 2], double a, double b, double* beta) {
+  if constexpr (S > P) {
+    return false;
+  } else {
+    if (u[S] < u[S + 1] && u[S] <= a && b <= u[S + 1]) {
+      bezier_span<P, S>(u, a, b, beta);
+      return true;
+    }
+    return bezier_spans<P, S + 1>(u, a, b, beta);
+  }
+}
+
+template <int P>
+__device__ inline bool bezier_1d_p(const double* ug, double a, double b, double* beta) {
+  double u[P + 2];
+#pragma unroll
+  for (int i = 0; i < P + 2; ++i) u[i] = ug[i];
+  return bezier_spans<P>(u, a, b, beta);
+}
+
+// Bernstein coefficients beta[0..p] of the B-spline with local knots
+// u[0..p+1] (global memory) on [a, b]; false if [a, b] is not inside one
+// non-empty knot span.
+__device__ inline bool bezier_1d(const double* u, int p, double a, double b, double* beta) {
+  switch (p) {
+    case 1: return bezier_1d_p<1>(u, a, b, beta);
+    case 2: return bezier_1d_p<2>(u, a, b, beta);
+    case 3: return bezier_1d_p<3>(u, a, b, beta);
+    default: return false;
+  }
 }
 
 // FP64 -> FP16 with a single round-to-nearest-even: round to odd in FP32
@@ -118,80 +153,90 @@ __global__ void range_final(unsigned long long* r) {
   d[1] = hi;
 }
 
+// One wavefront per element, looping over elements with the grid's stride.
+// The value range is folded into registers over all of a wavefront's
+// elements and merged into the global pair once per wavefront, and only if it
+// extends the pair as last seen: one global atomic per element on the same
+// two words serialised the whole launch.
 __global__ __launch_bounds__(kLanes) void extract_kernel(ExtractArgs a) {
   __shared__ double sb[kLanes][3][4];
   __shared__ double sw[kLanes][4];
   __shared__ double so[256];
-  const int64_t e = blockIdx.x;
   const int lane = threadIdx.x;
-  const int64_t b0 = a.csr_ptr[e], b1 = a.csr_ptr[e + 1];
-  const double* eb = a.elem_box + 6 * e;
   const int NC = a.nb * a.ncomp;
   const int px = a.p[0] + 1, py = a.p[1] + 1;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t base = b0; base < b1; base += kLanes) {
-    const int64_t q = base + lane;
-    if (q < b1) {
-      const int32_t bi = a.csr_idx[q];
-      bool ok = bi >= 0 && bi < a.n_bspl;
-      for (int d = 0; d < 3; ++d) {
-        double beta[4] = {0.0, 0.0, 0.0, 0.0};
-        if (ok) ok = bezier_1d(a.knots + ((int64_t)bi * 3 + d) * a.kstride, a.p[d], eb[d], eb[3 + d], beta);
-        for (int j = 0; j < 4; ++j) sb[lane][d][j] = beta[j];
+  double lo = INFINITY, hi = a.ncomp == 1 ? -INFINITY : 0.0;
+  for (int64_t e = blockIdx.x; e < a.n_elem; e += gridDim.x) {
+    const int64_t b0 = a.csr_ptr[e], b1 = a.csr_ptr[e + 1];
+    const double* eb = a.elem_box + 6 * e;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t base = b0; base < b1; base += kLanes) {
+      const int64_t q = base + lane;
+      if (q < b1) {
+        const int32_t bi = a.csr_idx[q];
+        bool ok = bi >= 0 && bi < a.n_bspl;
+        for (int d = 0; d < 3; ++d) {
+          double beta[4] = {0.0, 0.0, 0.0, 0.0};
+          if (ok) ok = bezier_1d(a.knots + ((int64_t)bi * 3 + d) * a.kstride, a.p[d], eb[d], eb[3 + d], beta);
+          for (int j = 0; j < 4; ++j) sb[lane][d][j] = beta[j];
+        }
+        for (int c = 0; c < 4; ++c)
+          sw[lane][c] = (ok && c < a.ncomp) ? a.gamma[bi] * a.coef[(int64_t)bi * a.ncomp + c] : 0.0;
       }
-      for (int c = 0; c < 4; ++c)
-        sw[lane][c] = (ok && c < a.ncomp) ? a.gamma[bi] * a.coef[(int64_t)bi * a.ncomp + c] : 0.0;
+      __syncthreads();
+      const int cnt = (int)((b1 - base) < kLanes ? (b1 - base) : kLanes);
+      for (int o = 0; o < 4; ++o) {
+        const int jj = lane + kLanes * o;
+        if (jj >= NC) break;
+        const int c = jj / a.nb, j = jj % a.nb;
+        const int jx = j % px, jy = (j / px) % py, jz = j / (px * py);
+        double s = acc[o];
+        for (int m = 0; m < cnt; ++m) s += sw[m][c] * sb[m][0][jx] * sb[m][1][jy] * sb[m][2][jz];
+        acc[o] = s;
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    const int cnt = (int)((b1 - base) < kLanes ? (b1 - base) : kLanes);
     for (int o = 0; o < 4; ++o) {
       const int jj = lane + kLanes * o;
-      if (jj >= NC) break;
-      const int c = jj / a.nb, j = jj % a.nb;
-      const int jx = j % px, jy = (j / px) % py, jz = j / (px * py);
-      double s = acc[o];
-      for (int m = 0; m < cnt; ++m) s += sw[m][c] * sb[m][0][jx] * sb[m][1][jy] * sb[m][2][jz];
-      acc[o] = s;
+      if (jj < NC) so[jj] = acc[o];
     }
     __syncthreads();
-  }
-  for (int o = 0; o < 4; ++o) {
-    const int jj = lane + kLanes * o;
-    if (jj < NC) so[jj] = acc[o];
-  }
-  __syncthreads();
-  for (int64_t jj = lane; jj < a.stride; jj += kLanes) {
-    const double v = jj < NC ? so[jj] : 0.0;
-    const int64_t off = e * a.stride + jj;
-    if (a.dtype == LR_F64)
-      static_cast<double*>(a.out)[off] = v;
-    else if (a.dtype == LR_F32)
-      static_cast<float*>(a.out)[off] = (float)v;
-    else
-      static_cast<unsigned short*>(a.out)[off] = f64_to_f16_bits(v);
-  }
-  if (a.range) {
-    double lo = INFINITY, hi = -INFINITY;
-    if (a.ncomp == 1) {
-      for (int jj = lane; jj < NC; jj += kLanes) {
-        lo = fmin(lo, so[jj]);
-        hi = fmax(hi, so[jj]);
-      }
-    } else {
-      lo = 0.0;
-      for (int j = lane; j < a.nb; j += kLanes) {
-        double n2 = 0.0;
-        for (int c = 0; c < a.ncomp; ++c) n2 += so[c * a.nb + j] * so[c * a.nb + j];
-        hi = fmax(hi, sqrt(n2));
+    for (int64_t jj = lane; jj < a.stride; jj += kLanes) {
+      const double v = jj < NC ? so[jj] : 0.0;
+      const int64_t off = e * a.stride + jj;
+      if (a.dtype == LR_F64)
+        static_cast<double*>(a.out)[off] = v;
+      else if (a.dtype == LR_F32)
+        static_cast<float*>(a.out)[off] = (float)v;
+      else
+        static_cast<unsigned short*>(a.out)[off] = f64_to_f16_bits(v);
+    }
+    if (a.range) {
+      if (a.ncomp == 1) {
+        for (int jj = lane; jj < NC; jj += kLanes) {
+          lo = fmin(lo, so[jj]);
+          hi = fmax(hi, so[jj]);
+        }
+      } else {
+        lo = 0.0;
+        for (int j = lane; j < a.nb; j += kLanes) {
+          double n2 = 0.0;
+          for (int c = 0; c < a.ncomp; ++c) n2 += so[c * a.nb + j] * so[c * a.nb + j];
+          hi = fmax(hi, sqrt(n2));
+        }
       }
     }
+    __syncthreads();   // so is rewritten by the next element
+  }
+  if (a.range) {
     for (int off = kLanes / 2; off > 0; off >>= 1) {
       lo = fmin(lo, __shfl_xor(lo, off));
       hi = fmax(hi, __shfl_xor(hi, off));
     }
     if (lane == 0) {
-      atomicMin(&a.range[0], dkey(lo));
-      atomicMax(&a.range[1], dkey(hi));
+      const unsigned long long klo = dkey(lo), khi = dkey(hi);
+      if (klo < __hip_atomic_load(&a.range[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(&a.range[0], klo);
+      if (khi > __hip_atomic_load(&a.range[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(&a.range[1], khi);
     }
   }
 }
@@ -296,7 +341,8 @@ LR_API lr_status lr_extract_bezier(const lr_lrspline* spl, int32_t out_dtype, vo
   a.range = reinterpret_cast<unsigned long long*>(range);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (range) hipLaunchKernelGGL(range_init, dim3(1), dim3(1), 0, st, a.range);
-  hipLaunchKernelGGL(extract_kernel, dim3((unsigned)spl->n_elem), dim3(kLanes), 0, st, a);
+  const int64_t grid = spl->n_elem < kExtractGrid ? spl->n_elem : kExtractGrid;
+  hipLaunchKernelGGL(extract_kernel, dim3((unsigned)grid), dim3(kLanes), 0, st, a);
   if (range) hipLaunchKernelGGL(range_final, dim3(1), dim3(1), 0, st, a.range);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return fail(LR_EHIP, "lr_extract_bezier: %s", hipGetErrorString(err));
