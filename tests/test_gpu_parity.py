@@ -71,6 +71,40 @@ def test_extraction_f64_matches_oracle(which):
         assert rng[0] == 0 and abs(rng[1] - np.linalg.norm(ref, axis=1).max()) <= 1e-12
 
 
+@pytest.mark.parametrize("name", ["blobs50k", "vortex200k"])
+def test_extraction_full_size_sampled(name):
+    """Full volumes (more elements than the extraction launch has wavefronts,
+    so each wavefront loops over several): seeded elements, the first and
+    last and those around the loop's stride, against the oracle's
+    interpolation; the reported value range equals the range of all FP64
+    blocks (merged across wavefronts)."""
+    import paper_1707_01170_amd as P
+    from oracle import bezier as obez
+    say("[gpu] extract full size", name)
+    wl = workload(name)
+    s = wl.spline
+    vol = P.Volume(s, blocks=4, dtype="f64")
+    got = vol.bezier.cpu().numpy()
+    n = s.n_elem
+    assert n > 8192
+    rng_ = np.random.default_rng(17)
+    pick = np.unique(np.concatenate([rng_.integers(0, n, 48), [0, 1, 8191, 8192, 8193, 16384, n - 8193, n - 1]]))
+    ref = obez.extract(s, oracle_parts(name)[0], elems=pick)
+    nc = ref.shape[1] * ref.shape[2]
+    g = got[pick, :nc].reshape(ref.shape)
+    err = np.abs(g - ref).max() / max(1.0, np.abs(ref).max())
+    say("%s extraction sampled max rel %.3e" % (name, err))
+    assert err <= 1e-12
+    assert np.all(got[:, nc:] == 0)
+    blocks = got[:, :nc].reshape(n, s.ncomp, -1)
+    r = vol.bez_range.cpu().numpy()
+    if s.ncomp == 1:
+        assert r[0] == blocks.min() and r[1] == blocks.max()
+    else:
+        top = np.sqrt((blocks ** 2).sum(axis=1)).max()
+        assert r[0] == 0 and abs(r[1] - top) <= 1e-14 * top
+
+
 def test_extraction_rounding_is_rne():
     import paper_1707_01170_amd as P
     s = _small_vector()
