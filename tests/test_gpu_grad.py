@@ -80,6 +80,94 @@ def test_backward_small_views():
     assert e_b <= TOL_F32 and e_l <= TOL_F32
 
 
+def _kink_samples(recs, lut, delta=1e-4):
+    """(record, sample) pairs whose table position lies within delta of a row
+    boundary where the table's slope jumps: there the row is decided by the
+    last bits of the value, so the FP32 kernel and the FP64 oracle may take
+    different rows, and both one-sided derivatives are valid."""
+    slope = np.diff(np.asarray(lut, dtype=np.float64), axis=0)
+    jump = np.zeros(257)
+    jump[1:255] = np.abs(np.diff(slope, axis=0)).max(1) > 1e-6      # boundary n: slope[n] vs slope[n - 1]
+    out = []
+    for k, r in enumerate(recs):
+        sv = r["st"][0]
+        n = np.rint(sv).astype(np.int64)
+        for m in np.nonzero((np.abs(sv - n) < delta) & (n > 0) & (n < 256))[0]:
+            if jump[n[m]]:
+                out.append((k, int(m)))
+    return out
+
+
+def _flip_row(recs, k, m):
+    import copy
+    recs = copy.deepcopy(recs)
+    S, i0, i1, w, inside = [np.array(x) for x in recs[k]["st"]]
+    n = int(np.rint(S[m]))
+    if S[m] >= n:
+        i0[m], i1[m], w[m] = n - 1, n, 1.0      # the row just below the boundary
+    else:
+        i0[m], i1[m], w[m] = n, min(n + 1, 255), 0.0
+    recs[k]["st"] = (S, i0, i1, w, inside)
+    return recs
+
+
+@pytest.mark.parametrize("p,mode", [(1, "adaptive"), (3, "adaptive"), (3, "fixed")])
+def test_backward_degrees_one_and_three(p, mode):
+    """The adjoint kernels of the other degrees (their LDS tables differ in
+    size: 8 and 64 coefficients per slot) against the oracle's reverse mode.
+    Samples whose table position lies on a slope kink of the table within
+    FP32 reach may take either row on either side: the oracle's gradient is
+    formed for every combination of those choices and the closest is used."""
+    import itertools
+    import lrgen
+    import paper_1707_01170_amd as P
+    from oracle import bezier as obez
+    from oracle import grad as ograd
+    from oracle.bspline import LREvaluator
+    from oracle.lookup import ElementIndex
+    say("[gpu] backward degree", p, mode)
+    s = lrgen.small_random(p=(p, p, p), n=(4, 4, 4), n_ref=40, seed=52 + p)
+    views = [lrgen.sphere_view([0.4, -0.6, 0.7], 30, 22), lrgen.sphere_view([-0.5, 0.2, 0.8], 18, 26)]
+    wl = lrgen.Workload("deg", s, lrgen.default_lut(), 0.0, 1.0, mode, 83, "lut", views)
+    C = obez.extract(s, LREvaluator(s))
+    ei = ElementIndex(s.elem_box)
+    rng = np.random.default_rng(7 + p)
+    data, gs, kinks = [], [], []
+    for vi, v in enumerate(views):
+        ii, jj = _grid(v)
+        rgba_o, _, recs = ograd.forward_records(wl, v, C, ei, ii=ii, jj=jj)
+        g = rng.normal(size=rgba_o.shape)
+        gs.append(g)
+        data.append([recs, ii.size, g])
+        kinks += [(vi, k, m) for k, m in _kink_samples(recs, wl.lut)]
+    assert len(kinks) <= 6
+    vol = P.Volume(s, blocks=4)
+    sc = P.Scene(vol, P.RenderParams.of(wl))
+    rgba, _, _ = P.render(sc, views)
+    g = torch.from_numpy(np.concatenate(gs).astype(np.float32)).cuda()
+    gb, gl = P.render_backward(sc, views, rgba, g)
+    torch.cuda.synchronize()
+    nc = (p + 1) ** 3
+    gb = gb.cpu().numpy()[:, :nc]
+    gl = gl.cpu().numpy()
+    best = None
+    for choice in itertools.product([False, True], repeat=len(kinks)):
+        gb_o = np.zeros_like(C)
+        gl_o = np.zeros((256, 4))
+        for vi, (recs, R, gv) in enumerate(data):
+            for (kv, k, m), flip in zip(kinks, choice):
+                if flip and kv == vi:
+                    recs = _flip_row(recs, k, m)
+            b, l = ograd.backward(wl, C, recs, R, gv)
+            gb_o += b
+            gl_o += l
+        e = (peak_rel(gb, gb_o[:, 0, :])[0], peak_rel(gl, gl_o)[0])
+        best = e if best is None or max(e) < max(best) else best
+    say("backward degree %d %s: dL/dC peak-rel %.3e, dL/dLUT %.3e (%d kink samples)" % (p, mode, best[0], best[1],
+                                                                                       len(kinks)))
+    assert best[0] <= TOL_F32 and best[1] <= TOL_F32
+
+
 def test_backward_full_size_sampled():
     """Full 4 x 512^2 launch; the upstream gradient is non-zero on seeded
     pixels only, which the oracle differentiates one by one."""
