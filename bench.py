@@ -308,7 +308,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--blocks", type=int, default=256)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16"])
-    ap.add_argument("--cpu-rays", type=int, default=65536, help="rays of the oracle CPU baseline (0: skip)")
+    ap.add_argument("--cpu-rays", type=int, default=524288, help="rays of the oracle CPU baseline (0: skip)")
     ap.add_argument("--copy-calib", action="store_true", help="also run a plain copy of known size (counter scale)")
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false", help="skip the adjoint step timing")
     ap.add_argument("--stream-study", action="store_true",
