@@ -243,15 +243,30 @@ def test_fp16_storage(name):
 
 
 def test_views_mixed_in_one_call():
-    """Several views of mixed size in one call equal the same views alone."""
+    """Views of mixed size in one call (20 views: two launches of at most 16)
+    equal the same views alone, forward bit for bit and the adjoint to float
+    atomics' reordering."""
     import paper_1707_01170_amd as P
+    from paper_1707_01170_amd import _lib as L
     wl, sc = scene("scalar20k")
     views = [resized(wl.views[i % 4], w, h) for i, (w, h) in enumerate([(40, 24), (17, 33), (64, 64), (8, 8)] * 5)]
+    assert len(views) > L.LR_MAX_VIEWS_PER_LAUNCH
     together, offs, _ = P.render(sc, views)
-    together = together.cpu().numpy()
-    for v, o in zip(views[:6], offs[:6]):
+    tg = together.cpu().numpy()
+    for v, o in zip(views, offs):
         alone, _, _ = P.render(sc, [v])
-        assert np.array_equal(together[o:o + v.width * v.height], alone.cpu().numpy())
+        assert np.array_equal(tg[o:o + v.width * v.height], alone.cpu().numpy())
+    g = torch.from_numpy(np.random.default_rng(4).normal(size=tg.shape).astype(np.float32)).cuda()
+    gb, gl = P.render_backward(sc, views, together, g)
+    sb, sl = torch.zeros_like(gb), torch.zeros_like(gl)
+    for v, o in zip(views, offs):
+        n = v.width * v.height
+        b, l = P.render_backward(sc, [v], together[o:o + n], g[o:o + n])
+        sb += b
+        sl += l
+    torch.cuda.synchronize()
+    assert peak_rel(gb.cpu().numpy(), sb.cpu().numpy())[0] <= 1e-5
+    assert peak_rel(gl.cpu().numpy(), sl.cpu().numpy())[0] <= 1e-5
 
 
 def test_bad_input_is_rejected():
