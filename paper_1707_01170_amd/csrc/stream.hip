@@ -4,9 +4,14 @@
 // embedded error control; the compute stage of Sec. 5.3 that fills a
 // seeds x samples buffer of (x, y, z, active).
 //
-// One lane integrates one seed.  The lane keeps its current element (box and
-// Bezier block in registers) like the ray caster and descends the look-up
-// structure only when a stage position leaves it.  Mixed precision (Sec. 5.6):
+// Three lanes integrate one seed (21 seeds per wavefront): all three carry the
+// same position, stages and step, and lane q evaluates only component q of the
+// field, from that component's part of the Bezier block, with the same
+// arithmetic as a whole-block contraction; the three values are exchanged by
+// lane shuffles.  This shortens each stage's dependent chain (the contraction
+// is most of it) and each lane loads a third of the block.  A group keeps its
+// current element like the ray caster and descends the look-up structure only
+// when a stage position leaves it.  Mixed precision (Sec. 5.6):
 // the position, time, step and stage sums are FP64 and only the field is
 // evaluated in FP32 from the FP32 Bezier block; single precision does the
 // outer loop in FP32 too.
@@ -123,13 +128,48 @@ struct Tab<LR_BS> {
   static constexpr double BL[4] = {7.0 / 24, 1.0 / 4, 1.0 / 3, 1.0 / 8};
 };
 
-// The field at stage positions, with the lane's current element cached.
+constexpr int kLanesPerSeed = 3;
+constexpr int kSeedsPerWave = 64 / kLanesPerSeed;   // lane 63 idles
+
+// Component q of the field at stage positions, with the group's current
+// element cached; f receives all three components.
 template <int P>
 struct Field {
   static constexpr int NB = (P + 1) * (P + 1) * (P + 1);
+  static constexpr int NW = (NB + 3) / 4 * 4 + 4;   // 16-byte aligned window holding one component
   float lo[3] = {2.0f, 2.0f, 2.0f}, hi[3] = {-1.0f, -1.0f, -1.0f}, inv[3] = {0.0f, 0.0f, 0.0f};
   float ds = 0.0f;    // Eq. 4 distance of the cached element
-  float c[Coef<3 * NB, float>::kRegs];
+  float c[NB];        // component q of the cached element's block
+  int q = 0;          // component of this lane
+  int lane0 = 0;      // first lane of the group
+
+  __device__ inline void load_component(const StreamK& k, int32_t e) {
+    // Component q starts at float q * NB of the row, not always 16-byte
+    // aligned: load the aligned window around it (inside the row, whose
+    // length is a multiple of 4 floats) and select with constant indices.
+    const float* row = k.bez + (int64_t)e * k.stride;
+    const int start = q * NB, a0 = start & ~3, off = start - a0;
+    const float4* r4 = reinterpret_cast<const float4*>(row + a0);
+    float w[NW];
+#pragma unroll
+    for (int i = 0; i < NW / 4; ++i) {
+      if (a0 + 4 * i < k.stride) {
+        const float4 v = r4[i];
+        w[4 * i] = v.x;
+        w[4 * i + 1] = v.y;
+        w[4 * i + 2] = v.z;
+        w[4 * i + 3] = v.w;
+      } else {
+        w[4 * i] = w[4 * i + 1] = w[4 * i + 2] = w[4 * i + 3] = 0.0f;
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < 4; ++o)
+      if (off == o) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) c[j] = w[j + o];
+      }
+  }
 
   template <typename R>
   __device__ inline void at(const StreamK& k, const R y[3], R f[3]) {
@@ -147,14 +187,17 @@ struct Field {
         inv[a] = __builtin_amdgcn_rcpf(hi[a] - lo[a]);
       }
       ds = fminf(fminf(hi[0] - lo[0], hi[1] - lo[1]), hi[2] - lo[2]) * (1.0f / (float)(1 << P));
-      Coef<3 * NB, float>::load(k.bez, k.stride, e, c);
+      load_component(k, e);
     }
     float bx[P + 1], by[P + 1], bz[P + 1];
     bernstein<P>(fminf(fmaxf((p[0] - lo[0]) * inv[0], 0.0f), 1.0f), bx);
     bernstein<P>(fminf(fmaxf((p[1] - lo[1]) * inv[1], 0.0f), 1.0f), by);
     bernstein<P>(fminf(fmaxf((p[2] - lo[2]) * inv[2], 0.0f), 1.0f), bz);
+    const float fq = contract<P, Coef<NB, float>>(c, 0, bx, by, bz);
+    // The three lanes of a group follow the same control flow (same state),
+    // so the lanes read here are active.
 #pragma unroll
-    for (int q = 0; q < 3; ++q) f[q] = (R)contract<P, Coef<3 * NB, float>>(c, q * NB, bx, by, bz);
+    for (int a = 0; a < 3; ++a) f[a] = (R)__shfl(fq, lane0 + a);
   }
 };
 
@@ -169,18 +212,23 @@ template <int P, int M, typename R>
 __global__ __launch_bounds__(64) void stream_kernel(const StreamK k) {
   using T = Tab<M>;
   constexpr int S = T::S;
-  const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const int grp = threadIdx.x / kLanesPerSeed;
+  if (grp >= kSeedsPerWave) return;
+  const int64_t j = (int64_t)blockIdx.x * kSeedsPerWave + grp;
   if (j >= k.n) return;
+  const bool writer = threadIdx.x == kLanesPerSeed * grp;   // lane 0 of the group stores the line
   float4* out = k.out + j * k.max_samples;
   double* tout = k.t_out ? k.t_out + j * k.max_samples : nullptr;
   R x[3];
   for (int a = 0; a < 3; ++a) x[a] = (R)k.seeds[3 * j + a];
   R t = 0;
   const R t_end = (R)k.t_end, base = (R)k.base, tol = (R)k.tol;
-  out[0] = make_float4((float)x[0], (float)x[1], (float)x[2], 1.0f);
-  if (tout) tout[0] = 0.0;
+  if (writer) out[0] = make_float4((float)x[0], (float)x[1], (float)x[2], 1.0f);
+  if (writer && tout) tout[0] = 0.0;
   int32_t n = 1;
   Field<P> fld;
+  fld.lane0 = kLanesPerSeed * grp;
+  fld.q = threadIdx.x - fld.lane0;
   R h_next = 0;
   bool first = true;
   while (n < k.max_samples && t < t_end) {
@@ -239,10 +287,11 @@ __global__ __launch_bounds__(64) void stream_kernel(const StreamK k) {
     if (!in) break;
     for (int a = 0; a < 3; ++a) x[a] = xn[a];
     t += h;
-    out[n] = make_float4((float)x[0], (float)x[1], (float)x[2], 1.0f);
-    if (tout) tout[n] = (double)t;
+    if (writer) out[n] = make_float4((float)x[0], (float)x[1], (float)x[2], 1.0f);
+    if (writer && tout) tout[n] = (double)t;
     ++n;
   }
+  if (!writer) return;
   if (k.count) k.count[j] = n;
   for (int32_t i = n; i < k.max_samples; ++i) {
     out[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -252,7 +301,7 @@ __global__ __launch_bounds__(64) void stream_kernel(const StreamK k) {
 
 template <int P, typename R>
 void launch_method(int32_t method, const StreamK& k, hipStream_t st) {
-  const dim3 grid((unsigned)((k.n + 63) / 64)), blk(64);
+  const dim3 grid((unsigned)((k.n + kSeedsPerWave - 1) / kSeedsPerWave)), blk(64);
   switch (method) {
     case LR_RK1: hipLaunchKernelGGL((stream_kernel<P, LR_RK1, R>), grid, blk, 0, st, k); break;
     case LR_RK2: hipLaunchKernelGGL((stream_kernel<P, LR_RK2, R>), grid, blk, 0, st, k); break;
