@@ -101,3 +101,24 @@ def test_full_size_sampled_headlight():
     say("headlight 1080p sampled: peak-rel %.3e rms %.3e" % (err, rms))
     assert np.array_equal(ns.cpu().numpy()[k] > 0, rns > 0)
     assert err <= TOL_F32
+
+
+@pytest.mark.parametrize("name,shading", [("vortex200k", "headlight"), ("blobs50k", "directional"),
+                                          ("vortex200k", "none"), ("blobs50k", "none"), ("scalar20k", "headlight")])
+def test_fp16_blocks_equal_fp32_kernel_on_widened_blocks(name, shading):
+    """FP16 blocks are widened exactly (inside each multiply-add, or when the
+    block is loaded in the illuminated vector kernel), so a render from FP16
+    blocks equals, bit for bit, the FP32 kernels' render of the same values
+    stored as FP32."""
+    import paper_1707_01170_amd as P
+    say("[gpu] fp16 == fp32 on widened blocks", name, shading)
+    wl, sc16 = scene(name, blocks=64, dtype="f16")
+    _, sc32 = scene(name, blocks=64)
+    view = resized(wl.views[0], 96, 60)
+    prm = dataclasses.replace(P.RenderParams.of(wl), shading=shading, light=(0.48, -0.6, 0.64))
+    a, _, _ = P.render(P.Scene(sc16.volume, prm), [view])
+    n32 = sc32.volume.bezier.shape[1]
+    widened = sc16.volume.bezier.float()[:, :n32].contiguous()
+    b, _, _ = P.render(P.Scene(sc32.volume, prm), [view], bezier=widened)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
