@@ -517,8 +517,10 @@ __global__ void lookup_octree_kernel(const uint32_t* __restrict__ root, const ui
 // Accumulation: a lane sums the gradient of consecutive samples of one
 // element in registers; on element change it adds the sum into a workgroup
 // hash table in LDS (the 64 rays of an 8x8 tile share most elements):
-// a slot is claimed for an element by compare-and-swap on its tag (linear
-// probing), values are added with LDS atomics, and the table is written to
+// a slot is claimed for an element by compare-and-swap on its tag when the
+// lane enters the element (its result is read when the lane leaves it; on a
+// collision the lane probes on then, linearly), values are added with LDS
+// atomics, and the table is written to
 // global memory with atomics once, when the workgroup ends (if it fills, the
 // lane adds to global memory directly).  Table gradients are summed in
 // registers while the table row stays the same, then added into an LDS copy
@@ -550,6 +552,8 @@ struct Adjoint : Composite {
   float range_scale;          // 255 / (vmax - vmin)
   const float4* lut;
   int32_t cur = -1;
+  uint32_t h_cur = 0;         // hash slot of cur
+  int32_t claim = -1;         // what the claim of h_cur found (-1: free, now cur's)
   float acc[NB];
   int32_t row = -1;           // table row i0 being accumulated
   float g0[4], g1[4];         // sums for rows i0 and min(i0 + 1, 255)
@@ -566,17 +570,25 @@ struct Adjoint : Composite {
 
   __device__ inline void flush_elem() {
     if (cur < 0) return;
-    uint32_t h = ((uint32_t)cur * 2654435761u) >> (32 - GradTable<P>::kLog2Slots);
-    for (int probe = 0; probe < GradTable<P>::kProbes; ++probe) {
-      int32_t t = htag[h];                          // same-address reads broadcast
-      if (t == -1) t = atomicCAS(&htag[h], -1, cur);
-      if (t == -1 || t == cur) {
-        double* v = hval + h * NB;
-#pragma unroll
-        for (int j = 0; j < NB; ++j) atomicAdd(v + j, (double)acc[j]);   // straight-line, no per-value branches
-        return;
+    int32_t slot = -1;
+    if (claim == -1 || claim == cur) {
+      slot = (int32_t)h_cur;
+    } else {
+      uint32_t h = (h_cur + 1) & (kSlots - 1);
+      for (int probe = 1; probe < GradTable<P>::kProbes; ++probe) {
+        const int32_t t = atomicCAS(&htag[h], -1, cur);
+        if (t == -1 || t == cur) {
+          slot = (int32_t)h;
+          break;
+        }
+        h = (h + 1) & (kSlots - 1);
       }
-      h = (h + 1) & (kSlots - 1);
+    }
+    if (slot >= 0) {
+      double* v = hval + slot * NB;
+#pragma unroll
+      for (int j = 0; j < NB; ++j) atomicAdd(v + j, (double)acc[j]);   // straight-line, no per-value branches
+      return;
     }
     float* out = gbez + (int64_t)cur * stride;
 #pragma unroll
@@ -618,6 +630,11 @@ struct Adjoint : Composite {
     if (sm.e != cur) {
       flush_elem();
       cur = sm.e;
+      // Claim the element's slot now; the result is first needed when the
+      // lane leaves the element, so the compare-and-swap's latency is hidden
+      // behind the element's samples.
+      h_cur = ((uint32_t)cur * 2654435761u) >> (32 - GradTable<P>::kLog2Slots);
+      claim = atomicCAS(&htag[h_cur], -1, cur);
 #pragma unroll
       for (int j = 0; j < NB; ++j) acc[j] = 0.0f;
     }
