@@ -185,3 +185,34 @@ def test_bench_configuration_sampled():
         same, len(pick), cnt.min(), cnt.max()))
     assert same >= 0.75 * len(pick)
     assert np.all(cnt >= 2) and cnt.max() <= 2048
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_other_degrees_match_oracle(p):
+    """Vector fields of degree 1 and 3: each lane of a seed's group loads its
+    component from a different offset of the block row (16-byte aligned for
+    these degrees, with the window clipped at the row's end); constant RK4
+    steps point by point against the oracle, mixed and single precision."""
+    import lrgen
+    import paper_1707_01170_amd as P
+    from oracle import streamline as ost
+    from oracle.bspline import LREvaluator
+    say("[gpu] streamline degree", p)
+    s = lrgen.small_random(p=(p, p, p), n=(4, 4, 4), n_ref=30, seed=60 + p, ncomp=3)
+    s = s.with_coef(s.coef - 0.5)                   # centred components: lines wander, few leave early
+    wl = lrgen.Workload("deg", s, lrgen.default_lut(), 0.0, 1.0, "adaptive", 64, "hue",
+                        [lrgen.sphere_view([0.3, -0.8, 0.5], 8, 8)])
+    sc = P.Scene(P.Volume(s, blocks=8), P.RenderParams.of(wl))
+    seeds = _seeds(40, 9)
+    ev = LREvaluator(s)
+    for prec, tol in (("mixed", 2e-6), ("single", 2e-5)):
+        kw = dict(method="rk4", step="constant", precision=prec, base=2.0 ** -7, t_end=0.125, max_samples=64)
+        pts, tim, cnt = P.streamlines(sc, seeds, **kw)
+        torch.cuda.synchronize()
+        pts, tim, cnt = pts.cpu().numpy(), tim.cpu().numpy(), cnt.cpu().numpy()
+        X, T, c = ost.integrate(lambda x: ev.evaluate(x), seeds, "rk4", "constant", kw["base"], kw["t_end"], 64)
+        assert np.array_equal(cnt, c) and c.max() == 17 and c.min() >= 2
+        for j in range(seeds.shape[0]):
+            n = c[j]
+            assert np.abs(pts[j, :n, :3] - X[j, :n]).max() <= tol, (prec, j)
+            assert np.all(pts[j, :n, 3] == 1.0) and np.all(pts[j, n:] == 0.0)
