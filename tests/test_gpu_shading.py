@@ -122,3 +122,23 @@ def test_fp16_blocks_equal_fp32_kernel_on_widened_blocks(name, shading):
     b, _, _ = P.render(P.Scene(sc32.volume, prm), [view], bezier=widened)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("name", ["blobs50k", "scalar20k"])
+def test_fp16_blocks_with_octree_equal_fp32_on_widened_blocks(name):
+    """The octree look-up with FP16 blocks: bit-identical to the FP32 octree
+    kernel on the widened blocks, and to the forest's FP16 render."""
+    import paper_1707_01170_amd as P
+    say("[gpu] fp16 octree", name)
+    wl = workload(name)
+    v16 = P.Volume(wl.spline, lookup="octree", dtype="f16")
+    v32 = P.Volume(wl.spline, lookup="octree")
+    view = resized(wl.views[0], 80, 48)
+    prm = P.RenderParams.of(wl)
+    a, _, _ = P.render(P.Scene(v16, prm), [view])
+    widened = v16.bezier.float()[:, :v32.bezier.shape[1]].contiguous()
+    b, _, _ = P.render(P.Scene(v32, prm), [view], bezier=widened)
+    _, sc16 = scene(name, blocks=64, dtype="f16")
+    c, _, _ = P.render(P.Scene(sc16.volume, prm), [view])
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(a, c)
