@@ -286,7 +286,7 @@ lr_status lr_render(const lr_scene* sc, const lr_view* views, int32_t n_views, f
                     uint32_t* nsamples, void* stream);
 
 /* Adjoint of lr_render for scalar fields (ncomp 1, LR_COLOR_LUT, F32 blocks,
- * forest look-up, no shading).
+ * either look-up structure, no shading).
  * Re-marches each ray with the forward's schedule (no per-sample storage) and
  * uses the forward image to form the suffix sums.  Accumulates (+=) into
  * grad_bezier (device float, the bezier layout) and grad_lut (device float

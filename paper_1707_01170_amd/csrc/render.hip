@@ -659,7 +659,7 @@ struct Adjoint : Composite {
   }
 };
 
-template <int P, int MODE>
+template <int P, int MODE, int LK>
 __global__ __launch_bounds__(kThreads) void backward_kernel(const SceneK s, const ViewsK vk, const float4* __restrict__ fwd,
                                                            const float4* __restrict__ grad, float* __restrict__ gbez,
                                                            float* __restrict__ glut) {
@@ -697,7 +697,7 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(const SceneK s, cons
       vis.hval = hval;
       vis.range_scale = 255.0f * s.inv_range;
       vis.lut = lut;
-      march<P, 1, float, MODE, LR_COLOR_LUT>(s, r, lut, vis);
+      march<P, 1, float, MODE, LR_COLOR_LUT, LK>(s, r, lut, vis);
     }
   }
   __syncthreads();
@@ -943,7 +943,6 @@ LR_API lr_status lr_render_backward(const lr_scene* sc, const lr_view* views, in
   if (st != LR_OK) return st;
   if (sc->ncomp != 1 || sc->color_mode != LR_COLOR_LUT || sc->bezier_dtype != LR_F32)
     return fail(LR_EINVAL, "lr_render_backward: scalar fields with FP32 blocks only");
-  if (sc->lookup != LR_LOOKUP_FOREST) return fail(LR_EINVAL, "lr_render_backward: forest look-up only");
   if (sc->shading != LR_SHADE_NONE) return fail(LR_EINVAL, "lr_render_backward: no shading");
   if (!views || n_views < 1 || !rgba_fwd || !grad_rgba || !grad_bezier || !grad_lut)
     return fail(LR_EINVAL, "lr_render_backward: null pointer or no views");
@@ -958,10 +957,16 @@ LR_API lr_status lr_render_backward(const lr_scene* sc, const lr_view* views, in
     const dim3 grid((unsigned)nblk), blk(kThreads);
     const float4* f = reinterpret_cast<const float4*>(rgba_fwd);
     const float4* g = reinterpret_cast<const float4*>(grad_rgba);
-    const bool fixed = sc->step_mode == LR_STEP_FIXED;
+    const bool fixed = sc->step_mode == LR_STEP_FIXED, oct = sc->lookup == LR_LOOKUP_OCTREE;
 #define LR_BWD(PP)                                                                                              \
-  if (fixed) hipLaunchKernelGGL((backward_kernel<PP, LR_STEP_FIXED>), grid, blk, 0, hs, s, vk, f, g, grad_bezier, grad_lut); \
-  else hipLaunchKernelGGL((backward_kernel<PP, LR_STEP_ADAPTIVE>), grid, blk, 0, hs, s, vk, f, g, grad_bezier, grad_lut);
+  if (oct && fixed) hipLaunchKernelGGL((backward_kernel<PP, LR_STEP_FIXED, LR_LOOKUP_OCTREE>), grid, blk, 0, hs, s, vk, f, g, \
+                                       grad_bezier, grad_lut);                                                     \
+  else if (oct) hipLaunchKernelGGL((backward_kernel<PP, LR_STEP_ADAPTIVE, LR_LOOKUP_OCTREE>), grid, blk, 0, hs, s, vk, f, g, \
+                                   grad_bezier, grad_lut);                                                         \
+  else if (fixed) hipLaunchKernelGGL((backward_kernel<PP, LR_STEP_FIXED, LR_LOOKUP_FOREST>), grid, blk, 0, hs, s, vk, f, g, \
+                                     grad_bezier, grad_lut);                                                       \
+  else hipLaunchKernelGGL((backward_kernel<PP, LR_STEP_ADAPTIVE, LR_LOOKUP_FOREST>), grid, blk, 0, hs, s, vk, f, g,         \
+                          grad_bezier, grad_lut);
     switch (sc->p[0]) {
       case 1: LR_BWD(1) break;
       case 2: LR_BWD(2) break;

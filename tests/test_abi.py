@@ -220,7 +220,7 @@ def test_render_rejects_bad_views():
     assert lib.lr_render(ctypes.byref(s), arr, 1, ctypes.c_void_p(0x1000), None, None) == L.LR_EINVAL
 
 
-def test_backward_rejects_vector_and_f16():
+def test_backward_rejects_vector_f16_and_shading():
     import lrgen
     lib = L.lib()
     arr, _ = P.api.view_array([lrgen.sphere_view([1, 0, 0], 8, 8)])
@@ -228,8 +228,6 @@ def test_backward_rejects_vector_and_f16():
     s = _scene_struct(ncomp=3, color_mode=L.LR_COLOR_HUE)
     assert lib.lr_render_backward(ctypes.byref(s), arr, 1, f, f, f, f, None) == L.LR_EINVAL
     s = _scene_struct(dtype=L.LR_F16)
-    assert lib.lr_render_backward(ctypes.byref(s), arr, 1, f, f, f, f, None) == L.LR_EINVAL
-    s = _scene_struct(lookup=L.LR_LOOKUP_OCTREE)
     assert lib.lr_render_backward(ctypes.byref(s), arr, 1, f, f, f, f, None) == L.LR_EINVAL
     s = _scene_struct(shading=L.LR_SHADE_HEADLIGHT)
     assert lib.lr_render_backward(ctypes.byref(s), arr, 1, f, f, f, f, None) == L.LR_EINVAL

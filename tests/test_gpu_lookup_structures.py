@@ -8,7 +8,7 @@ import pytest
 import torch
 
 from conftest import workload
-from gpu_util import oracle_parts, oracle_render, per_ray_schedule, resized, say
+from gpu_util import oracle_parts, oracle_render, peak_rel, per_ray_schedule, resized, say
 
 pytestmark = pytest.mark.gpu
 
@@ -99,12 +99,21 @@ def test_renders_identical_across_structures(name, w, h, other):
     assert int(a[2].sum()) > w * h
 
 
-def test_octree_rejects_backward():
+def test_octree_backward_equals_forest():
+    """The adjoint through the octree re-marches the same schedule as through
+    the forest, so the gradients agree up to the order of float atomics."""
     import paper_1707_01170_amd as P
-    from paper_1707_01170_amd import _lib as L
+    say("[gpu] octree backward")
     wl = workload("scalar20k")
-    sc = P.Scene(_vol("scalar20k", "octree"), P.RenderParams.of(wl))
-    view = resized(wl.views[0], 8, 8)
-    rgba, _, _ = P.render(sc, [view])
-    with pytest.raises(L.LRError):
-        P.render_backward(sc, [view], rgba, torch.zeros_like(rgba))
+    views = [resized(v, 64, 48) for v in wl.views]
+    so = P.Scene(_vol("scalar20k", "octree"), P.RenderParams.of(wl))
+    sf = P.Scene(_vol("scalar20k", "forest"), P.RenderParams.of(wl))
+    ro, _, _ = P.render(so, views)
+    rf, _, _ = P.render(sf, views)
+    assert torch.equal(ro, rf)
+    g = torch.from_numpy(np.random.default_rng(8).normal(size=tuple(ro.shape)).astype(np.float32)).cuda()
+    gbo, glo = P.render_backward(so, views, ro, g)
+    gbf, glf = P.render_backward(sf, views, rf, g)
+    torch.cuda.synchronize()
+    assert peak_rel(gbo.cpu().numpy(), gbf.cpu().numpy())[0] <= 1e-5
+    assert peak_rel(glo.cpu().numpy(), glf.cpu().numpy())[0] <= 1e-5
