@@ -113,11 +113,22 @@ def fd_lut(wl, view, C, eidx, ii, jj, target, row: int, ch: int, h: float = 1e-3
     return (out[0] - out[1]) / (2.0 * h)
 
 
+def kink_rows(lut: np.ndarray, tol: float = 1e-6) -> np.ndarray:
+    """Rows k (1..254) of the table where the slope of its linear interpolation
+    changes: LUT[k] - LUT[k-1] differs from LUT[k+1] - LUT[k] in some channel
+    by more than tol (the rounding of a linear ramp stored in FP32 is below
+    it).  Across any other row the interpolated table is one straight line."""
+    slope = np.diff(np.asarray(lut, dtype=np.float64), axis=0)
+    return np.nonzero(np.abs(np.diff(slope, axis=0)).max(axis=1) > tol)[0] + 1
+
+
 def kink_samples(wl, recs, e: int, j: int, h: float):
-    """Number of samples in element e whose table position s crosses an
-    integer (a kink of the linear interpolation) or a clamp when C[e,0,j]
-    moves by +-h; finite differences are not smooth there."""
+    """Number of samples in element e whose table position s crosses a row
+    where the table's slope changes (a kink of the linear interpolation) or a
+    clamp (s = 0 or 255) when C[e,0,j] moves by +-h; finite differences are
+    not smooth there."""
     sc = Scene.of(wl)
+    K = kink_rows(sc.lut)
     n = 0
     for r in recs:
         m = r["e"] == e
@@ -127,5 +138,7 @@ def kink_samples(wl, recs, e: int, j: int, h: float):
         s = r["st"][0][m]
         dsv = np.abs(B * h * 255.0 / (sc.vmax - sc.vmin))
         lo, hi = s - dsv, s + dsv
-        n += int(np.sum((np.floor(lo) != np.floor(hi)) | (lo <= 0) | (hi >= 255)))
+        k = np.searchsorted(K, lo, side="right")
+        crossed = (k < K.size) & (K[np.minimum(k, K.size - 1)] <= hi) if K.size else np.zeros(lo.shape, bool)
+        n += int(np.sum(crossed | (lo <= 0) | (hi >= 255)))
     return n

@@ -179,6 +179,12 @@ class BezierField:
         return obez.evaluate(self.p, self.C[e], self.box[e], x)
 
 
+def fixed_sample_t(t0: np.ndarray, dsf: np.ndarray, k: int) -> np.ndarray:
+    """Parameter of the k-th fixed-step sample: the midpoint of segment k of
+    N equal segments of length dsf starting at the entry t0 (FP32, R9)."""
+    return t0 + f32(k + 0.5) * dsf
+
+
 def render_rays(sc: Scene, elem_box, eidx: ElementIndex, field, o, d, t0, t1, hit,
                 mode: str = "S", record: bool = False):
     """Composite the rays (o, d) over [t0, t1).  mode 'S' follows the scene's
@@ -214,7 +220,7 @@ def render_rays(sc: Scene, elem_box, eidx: ElementIndex, field, o, d, t0, t1, hi
         dsf = (t1 - t0) / f32(N)
         for k in range(N):
             idx = np.nonzero(hit)[0]
-            t = t0[idx] + f32(k + 0.5) * dsf[idx]
+            t = fixed_sample_t(t0[idx], dsf[idx], k)
             x32 = positions(o[idx], d[idx], t)
             x = x32.astype(np.float64)
             e = eidx.find(x)

@@ -206,3 +206,65 @@ def test_heuristic_step_wrong_degree(monkeypatch):
 
     monkeypatch.setattr(ost, "heuristic_ds", bad)
     _fails(sp.test_lr_streamline_converges_to_exact)
+
+
+def test_positions_in_fp64(monkeypatch):
+    """Sample positions computed in FP64 instead of the FP32 replay (R11)."""
+    def bad(o, d, t):
+        return np.clip(o.astype(np.float64) + t[:, None].astype(np.float64) * d.astype(np.float64), 0.0, 1.0)
+
+    monkeypatch.setattr(orr, "positions", bad)
+    _fails(pins.test_sample_positions_on_ray, "adaptive")
+
+
+def test_positions_fused(monkeypatch):
+    """o + t d rounded once (a fused multiply-add) instead of twice."""
+    def bad(o, d, t):
+        p = (o.astype(np.float64) + t[:, None].astype(np.float64) * d.astype(np.float64)).astype(np.float32)
+        return np.clip(p, np.float32(0.0), np.float32(1.0))
+
+    monkeypatch.setattr(orr, "positions", bad)
+    _fails(pins.test_sample_positions_on_ray, "fixed")
+
+
+def test_fixed_samples_at_segment_starts(monkeypatch):
+    """Fixed steps sampled at the start of each segment instead of its midpoint."""
+    def bad(t0, dsf, k):
+        return t0 + np.float32(k) * dsf
+
+    monkeypatch.setattr(orr, "fixed_sample_t", bad)
+    _fails(pins.test_fixed_schedule_midpoints)
+
+
+def test_fixed_samples_off_by_one(monkeypatch):
+    """Fixed-step sample index shifted by one segment."""
+    def bad(t0, dsf, k):
+        return t0 + np.float32(k + 1.5) * dsf
+
+    monkeypatch.setattr(orr, "fixed_sample_t", bad)
+    _fails(pins.test_fixed_schedule_midpoints)
+
+
+def test_ray_direction_normalised_in_fp64(monkeypatch):
+    """Ray directions normalised in FP64 and rounded once instead of the FP32
+    operation sequence."""
+    good = ocam.primary_rays
+
+    def bad(view, ii, jj):
+        o, d, t0, t1, hit = good(view, ii, jj)
+        if view.proj == "persp":
+            sx = ((2 * np.asarray(ii) + 1) / view.width - 1.0) * float(view.tx)
+            sy = (1.0 - (2 * np.asarray(jj) + 1) / view.height) * float(view.ty)
+            dp = (view.fwd.astype(float) + sx[:, None] * view.right.astype(float)
+                  + sy[:, None] * view.up.astype(float))
+            d = (dp / np.linalg.norm(dp, axis=1, keepdims=True)).astype(np.float32)
+        return o, d, t0, t1, hit
+
+    monkeypatch.setattr(ocam, "primary_rays", bad)
+    _fails(pins.test_ray_setup_exact_replay)
+
+
+def test_fine_mode_too_coarse(monkeypatch):
+    """Mode F with a step 16x coarser no longer is the limit of fine fixed steps."""
+    monkeypatch.setattr(orr, "FINE_STEP", 2.0 ** -8)
+    _fails(pins.test_fixed_steps_converge_to_fine_mode)

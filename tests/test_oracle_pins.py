@@ -243,6 +243,169 @@ def test_perspective_rays_geometry():
     assert np.abs(d[c] - v.fwd).max() < 1e-6
 
 
+# ---------------------------------------------------------------- FP32 replay of rays and samples (R11)
+def _f32_round(q):
+    """The binary32 value nearest the rational q, ties to even, from the
+    format's definition (24-bit significand, exponents down to -126 with
+    subnormals below); independent of numpy's float32."""
+    from fractions import Fraction
+    q = Fraction(q)
+    if q == 0:
+        return 0.0
+    sign = -1 if q < 0 else 1
+    a = abs(q)
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    if Fraction(2) ** e > a:
+        e -= 1
+    e = max(e, -126)
+    ulp = Fraction(2) ** (e - 23)
+    m = a / ulp
+    n = m.numerator // m.denominator
+    r = m - n
+    if r > Fraction(1, 2) or (r == Fraction(1, 2) and n % 2 == 1):
+        n += 1
+    return sign * float(n * ulp)
+
+
+def _f32_sqrt(q):
+    """Correctly rounded binary32 square root of a non-negative rational."""
+    from fractions import Fraction
+    from math import isqrt
+    q = Fraction(q)
+    if q == 0:
+        return 0.0
+    # 60 extra bits: floor(sqrt(q) 2^60) with an exactness flag decides the rounding
+    k = 120
+    num = q.numerator << k
+    s = isqrt(num // q.denominator)
+    exact = s * s * q.denominator == num
+    lo = Fraction(s, 1 << 60)
+    # sqrt(q) lies in [lo, lo + 2^-60]; a binary32 rounding boundary can only be
+    # hit exactly when the root is exact, so nudging an inexact root by half a
+    # unit of the extra precision cannot change the rounded result
+    return _f32_round(lo if exact else lo + Fraction(1, 1 << 61))
+
+
+def _f32(v):
+    from fractions import Fraction
+    return Fraction(float(v))
+
+
+def test_ray_setup_exact_replay():
+    """Ray setup is one correctly rounded FP32 operation per operator of the
+    documented sequence (R11): replayed here in exact rational arithmetic with
+    a rounding written from the binary32 definition, ray by ray, bit for bit."""
+    from fractions import Fraction
+    for v in (lrgen.sphere_view([0.3, -0.8, 0.5], 37, 23), lrgen.sphere_view([-0.2, 0.1, 0.97], 19, 29)):
+        ii, jj = ocam.pixel_grid(v)
+        o, d, t0, t1, hit = ocam.primary_rays(v, ii, jj)
+        W, H = Fraction(v.width), Fraction(v.height)
+        rnd = _f32_round
+        for r in range(0, ii.size, 7):
+            sx = rnd(_f32(rnd(Fraction(2 * int(ii[r]) + 1) / W)) - 1)
+            sx = rnd(_f32(sx) * _f32(v.tx))
+            sy = rnd(1 - _f32(rnd(Fraction(2 * int(jj[r]) + 1) / H)))
+            sy = rnd(_f32(sy) * _f32(v.ty))
+            dp = [rnd(_f32(rnd(_f32(v.fwd[a]) + _f32(rnd(_f32(sx) * _f32(v.right[a]))))) +
+                      _f32(rnd(_f32(sy) * _f32(v.up[a])))) for a in range(3)]
+            sq = [rnd(_f32(x) * _f32(x)) for x in dp]
+            n = _f32_sqrt(_f32(rnd(_f32(rnd(_f32(sq[0]) + _f32(sq[1]))) + _f32(sq[2]))))
+            dd = [rnd(_f32(x) / _f32(n)) for x in dp]
+            assert [float(x) for x in d[r]] == dd, (r, d[r], dd)
+            assert [float(x) for x in o[r]] == [float(x) for x in v.eye]
+            # slab clip on the replayed ray
+            tn, tf, ok = Fraction(0), None, True
+            for a in range(3):
+                if dd[a] != 0.0:
+                    ta = rnd((0 - _f32(v.eye[a])) / _f32(dd[a]))
+                    tb = rnd((1 - _f32(v.eye[a])) / _f32(dd[a]))
+                    tn = max(tn, _f32(min(ta, tb)))
+                    tf = _f32(max(ta, tb)) if tf is None else min(tf, _f32(max(ta, tb)))
+                else:
+                    ok = ok and 0.0 <= float(v.eye[a]) <= 1.0
+            assert float(t0[r]) == float(tn) and float(t1[r]) == float(tf)
+            assert bool(hit[r]) == (ok and tn < tf)
+
+
+def _recorded(w, view, ii, jj):
+    """Every recorded sample (ray index, t, position) of a constant-field render."""
+    ev = LREvaluator(w.spline)
+    _, ns, recs = orr.render_view(w, view, orr.LRField(ev), ii=ii, jj=jj, record=True)
+    return ns, recs
+
+
+def _schedule_workload(mode, n_fixed=37):
+    import copy
+    w = _constant_workload(copy.copy(workload("scalar20k")), 77)
+    w.step_mode = mode
+    w.n_fixed_steps = n_fixed
+    return w
+
+
+@pytest.mark.parametrize("mode", ["fixed", "adaptive"])
+def test_sample_positions_on_ray(mode):
+    """Samples lie on the ray (R11): every position is an FP32 value in
+    [0,1]^3 within two FP32 roundings of the exact point clamp(o + t d); for a
+    perspective ray (unit d from the eye) an unclamped sample is at distance t
+    from the eye; a few hundred positions equal the exact rational replay of
+    fl(o + fl(t d)) bit for bit."""
+    from fractions import Fraction
+    w = _schedule_workload(mode)
+    view = lrgen.sphere_view([0.7, 0.2, -0.5], 18, 14)
+    ii, jj = ocam.pixel_grid(view)
+    o, d, t0, t1, hit = ocam.primary_rays(view, ii, jj)
+    ns, recs = _recorded(w, view, ii, jj)
+    assert hit.sum() > 50
+    n_exact = 0
+    for k, r in enumerate(recs):
+        idx, t, x = r["idx"], r["t"].astype(np.float64), r["x"]
+        assert np.array_equal(x.astype(np.float32).astype(np.float64), x)
+        assert np.all((x >= 0.0) & (x <= 1.0))
+        o64, d64 = o[idx].astype(np.float64), d[idx].astype(np.float64)
+        td = t[:, None] * d64
+        exact = o64 + td
+        bound = 2.0 ** -24 * (np.abs(td) + np.abs(exact))
+        assert np.all(np.abs(x - np.clip(exact, 0.0, 1.0)) <= bound)
+        inner = np.all((exact > 0.0) & (exact < 1.0), axis=1)
+        dist = np.sqrt(((exact[inner] - o64[inner]) ** 2).sum(1))
+        assert np.all(np.abs(dist - t[inner]) <= 1e-6 * t[inner])
+        if k % 3 == 0:
+            for m in range(0, idx.size, 5):
+                rep = [min(max(_f32_round(_f32(o[idx[m], a]) + _f32(_f32_round(_f32(r["t"][m]) * _f32(d[idx[m], a])))),
+                               0.0), 1.0) for a in range(3)]
+                assert list(x[m]) == rep, (k, m, x[m], rep)
+                n_exact += 1
+    assert n_exact > 100
+
+
+def test_fixed_schedule_midpoints():
+    """Fixed steps (R9): [t_entry, t_exit) is cut into N equal segments, each
+    sampled at its midpoint, so the samples are evenly spaced, sit half a
+    segment inside both ends, are symmetric about the ray's middle, and the
+    composited lengths are the one FP32 segment length (t_exit - t_entry)/N."""
+    N = 37
+    w = _schedule_workload("fixed", N)
+    view = lrgen.sphere_view([-0.3, 0.9, 0.4], 16, 12)
+    ii, jj = ocam.pixel_grid(view)
+    o, d, t0, t1, hit = ocam.primary_rays(view, ii, jj)
+    ns, recs = _recorded(w, view, ii, jj)
+    assert len(recs) == N and np.all(ns[hit] == N) and np.all(ns[~hit] == 0)
+    T = np.zeros((N, ii.size))
+    for k, r in enumerate(recs):
+        T[k, r["idx"]] = r["t"]
+        seg = (t1[r["idx"]] - t0[r["idx"]]) / np.float32(N)
+        assert np.array_equal(r["ds"], seg)
+    h = np.nonzero(hit)[0]
+    T = T[:, h]
+    a, b = t0[h].astype(np.float64), t1[h].astype(np.float64)
+    L = b - a
+    tol = 8 * 2.0 ** -24 * np.maximum(np.abs(a), np.abs(b))      # a few FP32 roundings of t
+    assert np.all(np.abs(np.diff(T, axis=0) - L / N) <= tol)
+    assert np.all(np.abs((T[0] - a) - 0.5 * L / N) <= tol)
+    assert np.all(np.abs((b - T[-1]) - 0.5 * L / N) <= tol)
+    assert np.all(np.abs(T + T[::-1] - (a + b)) <= 2 * tol)
+
+
 # ---------------------------------------------------------------- P5/P6 compositing
 def _constant_workload(wl, k):
     """The same mesh with every coefficient at the value mapping to LUT row k."""
@@ -289,6 +452,28 @@ def test_constant_field_closed_form(mode):
     assert np.abs(rgba[:, 3] - alpha).max() <= tol
     assert np.abs(rgba[:, :3] - alpha[:, None] * lut[k, :3]).max() <= tol
     assert hit.any() and (~hit).any()
+
+
+def test_fixed_steps_converge_to_fine_mode():
+    """Mode F (fixed fine step 2^-12, FP64 positions, its own loop) is the
+    limit of the fixed-step schedule (FP32 replay): both are midpoint sums of
+    the Eq. 3 integral composited by Alg. 2, so the difference falls as N
+    doubles, at the second order of the midpoint rule once N is large."""
+    import copy
+    s = lrgen.small_random(p=(2, 2, 2), n=(4, 4, 4), n_ref=30, seed=12)
+    w = lrgen.Workload("conv", s, lrgen.default_lut(), 0.0, 1.0, "fixed", 16, "lut",
+                       [lrgen.sphere_view([0.5, -0.7, 0.4], 10, 8)])
+    ev = LREvaluator(s)
+    F, _, _ = orr.render_view(w, w.views[0], orr.LRField(ev), mode="F")
+    errs = []
+    for N in (16, 64, 256, 512):
+        w2 = copy.copy(w)
+        w2.n_fixed_steps = N
+        S, _, _ = orr.render_view(w2, w2.views[0], orr.LRField(ev))
+        errs.append(np.abs(S - F).max())
+    assert errs[0] > errs[1] > errs[2] > errs[3]
+    assert errs[3] <= errs[0] / 1000.0 and errs[2] / errs[3] >= 3.0
+    assert errs[3] < 1e-5 * np.abs(F).max()
 
 
 def test_over_operator():
