@@ -64,24 +64,34 @@ def measured_traffic(blocks: int):
     return float(rec["traffic_bytes_per_launch"])
 
 
+# Algorithmic FP32 operations of one sample of the forward march (a fused
+# multiply-add counts 2, a transcendental 1): the 1-D Bernstein bases (6, 15,
+# 30 for p = 1, 2, 3), the tensor contraction 2((p+1)^3 + (p+1)^2 + (p+1))
+# per component, about 40 for the position, local coordinates, table look-up
+# and compositing (log1p/expm1 of the opacity correction), and for 3-vectors
+# |v| with its square root (6) and the azimuth hue (atan2, hexcone, about 30):
+# 133, 238 and 325 for the degree-2 scalar, degree-3 scalar and degree-2
+# vector samples.
 def flops_per_sample(p: int, ncomp: int) -> int:
-    """Algorithmic FP32 operations of one sample (transcendentals count 1):
-    position 6, local coordinates 6, Bernstein bases 3*(5 | 10), tensor
-    contraction 2*((p+1)^3+(p+1)^2+(p+1)) per component, table lookup 11,
-    compositing 13, and for 3-vectors |v| 6 and hue 7."""
-    bern = {1: 3 * 2, 2: 3 * 5, 3: 3 * 10}[p]
     q = p + 1
-    contr = 2 * (q ** 3 + q ** 2 + q) * ncomp
-    extra = 13 if ncomp == 3 else 0
-    return 6 + 6 + bern + contr + 11 + 13 + extra
+    bases = {1: 6, 2: 15, 3: 30}[p]
+    return bases + 2 * (q ** 3 + q ** 2 + q) * ncomp + 40 + (36 if ncomp == 3 else 0)
+
+
+# The adjoint re-marches the forward (the forward's count) and per sample forms
+# the compositing derivative (prefix/suffix terms, about 40), the table-row
+# sums and slope (about 30) and scatters dv/dC_j = B_j(u) into the element's
+# gradient (2 (p+1)^3 + 2 (p+1)^2 + ...: 72 for p = 2).
+ADJOINT_EXTRA_FLOPS = {1: 40 + 30 + 24, 2: 40 + 30 + 72, 3: 40 + 30 + 160}
 
 
 def cpu_baseline(wl, n_rays: int, seed: int = 11):
     """The FP64 oracle (schedule-matched mode) on n_rays seeded pixels of the
-    view, split over a fork pool of the host cores; returns samples/s."""
+    view, split over a fork pool of the host cores.  Returns samples/s, the
+    cores used, the samples, the wall time, and the pixels with their oracle
+    RGBA (compared with the GPU frames afterwards)."""
     import multiprocessing as mp
 
-    from oracle import render as orr
     from oracle.bspline import LREvaluator
     from oracle.lookup import ElementIndex
     view = wl.views[0]
@@ -95,9 +105,11 @@ def cpu_baseline(wl, n_rays: int, seed: int = 11):
     _CPU_JOB = (wl, view, ev, ei, ii, jj)
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(cores) as pool:
-        counts = pool.map(_cpu_chunk, chunks)
+        parts = pool.map(_cpu_chunk, chunks)
     dt = time.perf_counter() - t0
-    return float(sum(counts)) / dt, cores, int(sum(counts)), dt
+    counts = sum(c for c, _ in parts)
+    rgba = np.concatenate([r for _, r in parts])
+    return float(counts) / dt, cores, int(counts), dt, (ii, jj, rgba)
 
 
 _CPU_JOB = None
@@ -106,8 +118,22 @@ _CPU_JOB = None
 def _cpu_chunk(idx):
     from oracle import render as orr
     wl, view, ev, ei, ii, jj = _CPU_JOB
-    _, ns, _ = orr.render_view(wl, view, orr.LRField(ev), eidx=ei, ii=ii[idx], jj=jj[idx])
-    return int(ns.sum())
+    rgba, ns, _ = orr.render_view(wl, view, orr.LRField(ev), eidx=ei, ii=ii[idx], jj=jj[idx])
+    return int(ns.sum()), rgba
+
+
+def accuracy(frame, view, oracle_pix):
+    """Peak-relative max and RMS difference of a GPU frame's pixels to the
+    oracle's RGBA of the same pixels (max |x - ref| / max |ref|)."""
+    ii, jj, ref = oracle_pix
+    got = frame.view(view.height, view.width, 4)[torch_index(jj), torch_index(ii)].cpu().numpy().astype(np.float64)
+    scale = np.abs(ref).max()
+    return {"max": float(np.abs(got - ref).max() / scale), "rms": float(np.sqrt(((got - ref) ** 2).mean()) / scale)}
+
+
+def torch_index(a):
+    import torch
+    return torch.from_numpy(np.asarray(a, dtype=np.int64))
 
 
 def adjoint_step(dev, steps: int = 10):
@@ -157,14 +183,47 @@ def adjoint_step(dev, steps: int = 10):
         vol.extract_backward(g)
     xb.record()
     torch.cuda.synchronize()
+    # the adjoint kernel alone: lr_render_backward into preallocated gradients
+    # (it accumulates, so no clearing inside the timed region)
+    import ctypes
+    from paper_1707_01170_amd import _lib as L
+    from paper_1707_01170_amd.api import view_array
+    arr, _ = view_array(wl.views)
+    gup = torch.randn_like(rgba)
+    gbz = torch.zeros_like(vol.bezier)
+    glt = torch.zeros((256, 4), dtype=torch.float32, device=dev)
+    scs = sc.struct()
+    st = torch.cuda.current_stream(dev)
+    hs = ctypes.c_void_p(st.cuda_stream)
+
+    def bwd():
+        L.check(L.lib().lr_render_backward(ctypes.byref(scs), arr, len(wl.views), ctypes.c_void_p(rgba.data_ptr()),
+                                           ctypes.c_void_p(gup.data_ptr()), ctypes.c_void_p(gbz.data_ptr()),
+                                           ctypes.c_void_p(glt.data_ptr()), hs))
+    for _ in range(2):
+        bwd()
+    ka, kb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ka.record(st)
+    for _ in range(steps):
+        bwd()
+    kb.record(st)
+    torch.cuda.synchronize()
     ms = a.elapsed_time(b) / steps
     fms = fa.elapsed_time(fb) / steps
     xms = xa.elapsed_time(xb) / steps
-    log("adjoint: forward+loss+backward %.3f ms (forward alone %.3f ms), %d samples per forward; "
-        "extraction adjoint %.3f ms" % (ms, fms, samples, xms))
+    bms = ka.elapsed_time(kb) / steps
+    fl = flops_per_sample(vol.p[0], 1) + ADJOINT_EXTRA_FLOPS[vol.p[0]]
+    achieved = fl * samples / (bms / 1e3) / 1e12
+    log("adjoint: forward+loss+backward %.3f ms (forward alone %.3f ms, adjoint kernel %.3f ms), %d samples per "
+        "forward; extraction adjoint %.3f ms; adjoint %.2f TFLOP/s (%.1f%% of %.1f)"
+        % (ms, fms, bms, samples, xms, achieved, 100 * achieved / PEAK_FP32_TFLOPS, PEAK_FP32_TFLOPS))
     return {"workload": "scalar (2,2,2), %d elements, 4 x 512^2 views, L2 loss, grad wrt Bezier blocks and table"
-                        % vol.n_elem, "step_ms": ms, "forward_ms": fms, "samples_per_forward": samples,
-            "samples_per_s_fwd_bwd": samples / (ms / 1e3), "extraction_adjoint_ms": xms}
+                        % vol.n_elem, "step_ms": ms, "forward_ms": fms, "backward_kernel_ms": bms,
+            "samples_per_forward": samples, "samples_per_s_fwd_bwd": samples / (ms / 1e3),
+            "extraction_adjoint_ms": xms,
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / PEAK_FP32_TFLOPS, "flops_per_sample": fl,
+                         "kernel": "backward_kernel (re-march + adjoint)"}}
 
 
 def lookup_sweep(dev, name: str, steps: int = 10):
@@ -281,7 +340,10 @@ def stream_lines(sc, n_seeds: int = 16384, study: bool = False):
 
 def serve_stream(n_req: int, dev):
     """The request stream on the (3,3,3) blob volume with FP16 Bezier storage:
-    Poisson arrivals at 200/s, square views of 256..2048, continuous batching."""
+    Poisson arrivals at 200/s, square views of 256..2048, continuous batching.
+    Then the same requests with the arrival times compressed (time_scale < 1
+    raises the offered rate; 0 offers everything at once), to find the rate
+    the server sustains and how batching and latency respond to load."""
     import lrgen
     import paper_1707_01170_amd as P
     from paper_1707_01170_amd.serve import Server
@@ -291,14 +353,26 @@ def serve_stream(n_req: int, dev):
     reqs = lrgen.blob_requests(n=n_req)
     warm = Server(sc, budget_bytes=2 << 30).run(reqs[:8])
     log("serving: warm-up %d requests" % warm.n)
-    st = Server(sc, budget_bytes=2 << 30, n_streams=3).run(reqs)
+    srv = Server(sc, budget_bytes=2 << 30, n_streams=3)
+    st = srv.run(reqs)
     log("serving: %d requests, p50 %.1f ms p99 %.1f ms, offered %.3g px/s served %.3g px/s, %d launches"
         % (st.n, st.p50_ms, st.p99_ms, st.offered_px_per_s, st.served_px_per_s, st.launches))
+    sweep = []
+    for scale in (0.5, 0.25, 0.1, 0.03, 0.0):
+        r = srv.run(reqs, time_scale=scale)
+        offered = r.offered_px_per_s if scale > 0 else None
+        sweep.append({"time_scale": scale, "offered_px_per_s": offered, "served_px_per_s": r.served_px_per_s,
+                      "p50_ms": r.p50_ms, "p99_ms": r.p99_ms, "launches": r.launches,
+                      "views_per_launch": r.mean_views_per_launch, "max_inflight": r.max_inflight})
+        log("serving load x%s: offered %s px/s, served %.3g px/s, %.2f views/launch, p50 %.1f ms p99 %.1f ms"
+            % ("inf" if scale == 0 else "%.3g" % (1 / scale), "all at once" if offered is None else "%.3g" % offered,
+               r.served_px_per_s, r.mean_views_per_launch, r.p50_ms, r.p99_ms))
     return {"workload": "blob volume (3,3,3) scalar, %d elements, FP16 blocks / FP32 arithmetic; %d requests, "
                         "Poisson 200/s, square 256..2048" % (vol.n_elem, st.n),
             "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_ms": st.mean_ms, "offered_px_per_s": st.offered_px_per_s,
             "served_px_per_s": st.served_px_per_s, "wall_s": st.wall_s, "launches": st.launches,
-            "views_per_launch": st.mean_views_per_launch, "budget_bytes": 2 << 30}
+            "views_per_launch": st.mean_views_per_launch, "budget_bytes": 2 << 30,
+            "load_sweep": sweep, "saturated_px_per_s": sweep[-1]["served_px_per_s"]}
 
 
 def main():
@@ -327,10 +401,10 @@ def main():
     log("generating workload")
     wl = lrgen.cached("vortex200k")
     view = wl.views[0]
-    cpu = None
+    cpu = oracle_pix = None
     if args.cpu_rays > 0:       # before any GPU initialisation (the pool forks)
         log("oracle CPU baseline on %d rays" % args.cpu_rays)
-        sps, cores, nsmp, dt = cpu_baseline(wl, args.cpu_rays)
+        sps, cores, nsmp, dt, oracle_pix = cpu_baseline(wl, args.cpu_rays)
         cpu = {"value": sps, "unit": "samples/s", "cores": cores, "kind": "oracle",
                "sample": "%d seeded rays of the 1920x1080 view (%d samples, %.1f s), FP64, schedule-matched"
                          % (args.cpu_rays, nsmp, dt)}
@@ -374,6 +448,11 @@ def main():
     times = np.array([a.elapsed_time(b) for a, b in ev])      # ms, per launch, on the launch stream
     log("frame ms: mean %.3f p50 %.3f p99 %.3f; wall %.3f s" % (times.mean(), np.percentile(times, 50),
                                                                np.percentile(times, 99), wall))
+    acc = None
+    if oracle_pix is not None:     # the timed frame against the oracle's pixels
+        acc = {args.dtype: accuracy(out, view, oracle_pix), "rays": int(oracle_pix[0].size)}
+        log("accuracy of the timed frame (%s blocks) on %d oracle rays: peak-relative max %.2e rms %.2e"
+            % (args.dtype, acc["rays"], acc[args.dtype]["max"], acc[args.dtype]["rms"]))
     # FP16 Bezier storage with FP32 arithmetic: the same frame
     vol16 = P.Volume(wl.spline, blocks=args.blocks, dtype="f16", device=dev)
     sc16 = P.Scene(vol16, P.RenderParams.of(wl))
@@ -391,6 +470,10 @@ def main():
     log("FP16 blocks: %.3f ms per frame (%.2fx), peak-relative difference to FP32 %.2e" % (f16_ms, times.mean() / f16_ms, f16_diff))
     fp16 = {"storage": "FP16 Bezier blocks, FP32 arithmetic", "ms_per_frame": f16_ms,
             "samples_per_s": samples / (f16_ms / 1e3), "peak_rel_diff_vs_f32": f16_diff}
+    if oracle_pix is not None:
+        acc["f16"] = accuracy(out16, view, oracle_pix)
+        fp16["vs_oracle"] = acc["f16"]
+        log("FP16 blocks against the oracle: peak-relative max %.2e rms %.2e" % (acc["f16"]["max"], acc["f16"]["rms"]))
     del vol16, sc16, out16
     # local illumination (Sec. 4.1): the same frame with a head light
     import dataclasses
@@ -448,8 +531,11 @@ def main():
         "p99_ms": float(np.percentile(times, 99)),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
-                     "hbm_GBps": None if traffic is None else traffic / kern_s / 1e9,
+                     # FETCH_SIZE + WRITE_SIZE count L2 <-> fabric traffic (Infinity
+                     # Cache hits included), an upper bound on the HBM bytes
+                     "l2_fabric_GBps": None if traffic is None else traffic / kern_s / 1e9,
                      "flops_per_sample": flops_per_sample(vol.p[0], vol.ncomp), "kernel_ms": times.mean()},
+        "accuracy": acc,
         "cpu_baseline": cpu,
         "serving": serving,
         "adjoint": adjoint,

@@ -132,6 +132,27 @@ lr_status lr_forest_export(const lr_forest_host* f, uint32_t* heads, lr_kdnode* 
 
 void lr_forest_free(lr_forest_host* f);
 
+/* The same build written into caller device buffers, in two phases.
+ * elem_box  host float [n_elem][6] (values in [0,1]; the same checks as above)
+ * blocks    host int32[3], each a power of two in [1, 512]
+ * Phase 1: d_heads = d_nodes = NULL: builds and returns the sizes
+ *          (*n_nodes_out; stats_out->n_heads = bx*by*bz and the depth
+ *          statistics), writes nothing else.
+ * Phase 2: d_heads device uint32 [bx*by*bz], d_nodes device lr_kdnode
+ *          [nodes_cap] (may be NULL when the forest has no nodes, with
+ *          nodes_cap 0): builds again, fails with LR_ECAPACITY if nodes_cap is
+ *          below the node count, copies heads and nodes on `stream` and
+ *          returns once the copies have completed (the host arrays are freed
+ *          then).  The device layout is the one lr_lookup and lr_render read. */
+lr_status lr_build_forest_device(const float* elem_box, int64_t n_elem, const int32_t blocks[3], uint32_t* d_heads,
+                                 lr_kdnode* d_nodes, int64_t nodes_cap, int64_t* n_nodes_out,
+                                 lr_forest_stats* stats_out, void* stream);
+
+/* SHA-1 (hex) of the library sources and compile flags this binary was built
+ * from ("unknown" if the build did not define it): lets a binding refuse, or
+ * rebuild, a binary older than its sources. */
+const char* lr_build_id(void);
+
 /* Element ids of n points (device float [n][3], each coordinate in [0,1])
  * by Alg. 1 over a forest uploaded to the device; elem_out device int32 [n]. */
 lr_status lr_lookup(const uint32_t* heads, const lr_kdnode* nodes, int64_t n_nodes,

@@ -35,6 +35,22 @@ def _torch_lib_dir():
     return None
 
 
+def source_digest() -> str:
+    """SHA-1 of everything the library is compiled from: the sources under
+    csrc/, the C header and the compile flags."""
+    import hashlib
+    h = hashlib.sha1()
+    files = sorted(glob.glob(os.path.join(CSRC, "*")))
+    files.append(os.path.join(os.path.dirname(HERE), "include", "lrvr.h"))
+    for path in files:
+        if os.path.isfile(path):
+            h.update(os.path.basename(path).encode())
+            with open(path, "rb") as f:
+                h.update(f.read())
+    h.update(" ".join(HIPCC_FLAGS).encode())
+    return h.hexdigest()
+
+
 def build(verbose: bool = False) -> str:
     """Compiles every source to an object (in parallel) and links the shared
     library; each object carries its own gfx950 code object."""
@@ -42,7 +58,7 @@ def build(verbose: bool = False) -> str:
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
     objdir = os.path.join(HERE, "_obj")
     os.makedirs(objdir, exist_ok=True)
-    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"] + ['-DLR_BUILD_ID="%s"' % source_digest()]
 
     def compile_one(src):
         obj = os.path.join(objdir, os.path.basename(src) + ".o")

@@ -69,6 +69,9 @@ SIGNATURES = {
     "lr_build_forest": (_c_i32, [_vp, _c_i64, _vp, ctypes.POINTER(_vp), ctypes.POINTER(ForestStats)]),
     "lr_forest_export": (_c_i32, [_vp, _vp, _vp]),
     "lr_forest_free": (None, [_vp]),
+    "lr_build_forest_device": (_c_i32, [_vp, _c_i64, _vp, _vp, _vp, _c_i64, ctypes.POINTER(_c_i64),
+                                        ctypes.POINTER(ForestStats), _vp]),
+    "lr_build_id": (ctypes.c_char_p, []),
     "lr_lookup": (_c_i32, [_vp, _vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _vp, _vp]),
     "lr_build_octree": (_c_i32, [_vp, _c_i64, ctypes.POINTER(_vp), ctypes.POINTER(ForestStats)]),
     "lr_octree_export": (_c_i32, [_vp, _vp, _vp]),
@@ -96,12 +99,28 @@ class LRError(RuntimeError):
         self.status = status
 
 
+def _built_id(path):
+    """The build id a library file reports (read in a child process, so that
+    a stale binary is never loaded into this one)."""
+    import subprocess
+    import sys
+    code = ("import ctypes,sys; L=ctypes.CDLL(sys.argv[1]); f=L.lr_build_id; f.restype=ctypes.c_char_p; "
+            "print(f().decode())")
+    r = subprocess.run([sys.executable, "-c", code, path], capture_output=True, text=True)
+    return r.stdout.strip() if r.returncode == 0 else None
+
+
 def lib():
-    """The loaded HIP library.  Builds it in-tree if it was never built; raises
-    if that fails (there is no fallback implementation)."""
+    """The loaded HIP library.  Builds it in-tree if it was never built or was
+    built from other sources than the ones in the tree (its lr_build_id differs
+    from their digest); raises if that fails (there is no fallback
+    implementation)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        want = _build.source_digest()
+        if not os.path.exists(_build.LIB) or _built_id(_build.LIB) != want:
+            import sys
+            print("[lrvr] building %s (sources changed since it was built)" % _build.LIB, file=sys.stderr, flush=True)
             _build.build()
         import torch  # noqa: F401  (loads the HIP runtime the library links against)
         L = ctypes.CDLL(_build.LIB)
@@ -109,6 +128,9 @@ def lib():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
+        got = L.lr_build_id().decode()
+        if got != want:
+            raise RuntimeError("%s reports build %s, its sources are %s" % (_build.LIB, got, want))
         _lib = L
     return _lib
 

@@ -57,6 +57,25 @@ class Forest:
         return Forest(tuple(int(x) for x in b), heads, nodes, stats)
 
 
+def build_forest_device(elem_box: np.ndarray, blocks, device=None):
+    """The k-d forest built on the host and written into device tensors by
+    lr_build_forest_device (size query, then build and copy on the current
+    stream).  Returns (heads int32 [n_heads], nodes int32 [n_nodes, 4], stats)."""
+    lib = L.lib()
+    dev = torch.device(device if device is not None else "cuda")
+    eb = np.ascontiguousarray(elem_box, dtype=np.float32)
+    b = np.asarray((blocks,) * 3 if isinstance(blocks, int) else blocks, dtype=np.int32)
+    n_nodes = ctypes.c_int64()
+    st = L.ForestStats()
+    L.check(lib.lr_build_forest_device(_np_ptr(eb), eb.shape[0], _np_ptr(b), None, None, 0, ctypes.byref(n_nodes),
+                                       ctypes.byref(st), None))
+    heads = torch.empty(st.n_heads, dtype=torch.int32, device=dev)
+    nodes = torch.empty((max(n_nodes.value, 1), 4), dtype=torch.int32, device=dev)
+    L.check(lib.lr_build_forest_device(_np_ptr(eb), eb.shape[0], _np_ptr(b), _ptr(heads), _ptr(nodes),
+                                       nodes.shape[0], ctypes.byref(n_nodes), ctypes.byref(st), _stream(dev)))
+    return heads, nodes[:n_nodes.value], {k: getattr(st, k) for k, _ in L.ForestStats._fields_}
+
+
 @dataclass
 class Octree:
     """Element octree of a dyadic mesh, built on the host (Sec. 3.2)."""

@@ -23,7 +23,12 @@ lr_status fail(lr_status st, const char* fmt, ...) {
 
 LR_API const char* lr_last_error(void) { return lrvr::g_last_error.c_str(); }
 
-LR_API int32_t lr_version(void) { return 100; }
+LR_API int32_t lr_version(void) { return 200; }
+
+#ifndef LR_BUILD_ID
+#define LR_BUILD_ID "unknown"
+#endif
+LR_API const char* lr_build_id(void) { return LR_BUILD_ID; }
 
 LR_API int64_t lr_bezier_stride(const int32_t p[3], int32_t ncomp, int32_t dtype) {
   if (!p || ncomp < 1) return -1;

@@ -1,7 +1,7 @@
-// Device-side look-up and Bezier evaluation shared by the ray caster and the
-// streamline integrator: the forest descent of Alg. 1 (Sec. 3.2.1), the
-// octree descent (Sec. 3.2.2), loading of an element's Bezier block and its
-// tensor Bernstein evaluation with optional gradient (Sec. 3.2.3).
+// Device-side evaluation shared by the ray caster and the streamline
+// integrator: loading of an element's Bezier block and its tensor Bernstein
+// evaluation with optional gradient (Sec. 3.2.3).  The look-up descents
+// (Alg. 1 and the octree) are in lookup.h.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,6 +9,7 @@
 #include <cstring>
 
 #include "common.h"
+#include "lookup.h"
 
 namespace lrvr {
 
@@ -16,46 +17,6 @@ __device__ inline bool inside(const float p[3], const float lo[3], const float h
   bool in = true;
   for (int a = 0; a < 3; ++a) in = in && lo[a] <= p[a] && (p[a] < hi[a] || (p[a] == 1.0f && hi[a] == 1.0f));
   return in;
-}
-
-// ---------------------------------------------------------------- Alg. 1
-__device__ inline int32_t forest_lookup(const uint32_t* __restrict__ heads, const lr_kdnode* __restrict__ nodes,
-                                        int64_t n_nodes, int64_t n_elem, int32_t bx, int32_t by, int32_t bz,
-                                        float fbx, float fby, float fbz, const float p[3]) {
-  const int ix = min((int)(p[0] * fbx), bx - 1);
-  const int iy = min((int)(p[1] * fby), by - 1);
-  const int iz = min((int)(p[2] * fbz), bz - 1);
-  uint32_t r = heads[((int64_t)iz * by + iy) * bx + ix];
-  for (int guard = 0; guard < 256 && !(r & LR_LEAF); ++guard) {
-    if ((int64_t)r >= n_nodes) break;
-    const uint4 nd = reinterpret_cast<const uint4*>(nodes)[r];
-    const float split = __uint_as_float(nd.z);
-    const float v = nd.w == 0 ? p[0] : (nd.w == 1 ? p[1] : p[2]);
-    r = v < split ? nd.x : nd.y;
-  }
-  const int64_t e = (r & LR_LEAF) ? (int64_t)(r & ~LR_LEAF) : 0;
-  return e < n_elem ? (int32_t)e : 0;
-}
-
-// Octree descent (dyadic meshes): one 4-byte child reference per level; the
-// child of a level-l cell is picked by bit l+1 of floor(p * 2^(l+1)) per axis
-// (exact in FP32: p is scaled by a power of two).
-__device__ inline int32_t octree_lookup(const uint32_t* __restrict__ root, const uint32_t* __restrict__ nodes,
-                                        int64_t n_nodes, int64_t n_elem, const float p[3]) {
-  uint32_t r = root[0];
-  float scale = 2.0f;
-  int lim = 1;
-  for (int level = 0; level < 24 && !(r & LR_LEAF); ++level) {
-    if ((int64_t)r >= n_nodes) break;
-    const int cx = min((int)(p[0] * scale), lim) & 1;
-    const int cy = min((int)(p[1] * scale), lim) & 1;
-    const int cz = min((int)(p[2] * scale), lim) & 1;
-    r = nodes[8 * (int64_t)r + (cx | (cy << 1) | (cz << 2))];
-    scale *= 2.0f;
-    lim = 2 * lim + 1;
-  }
-  const int64_t e = (r & LR_LEAF) ? (int64_t)(r & ~LR_LEAF) : 0;
-  return e < n_elem ? (int32_t)e : 0;
 }
 
 // ---------------------------------------------------------------- Bezier blocks

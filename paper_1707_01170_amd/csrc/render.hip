@@ -250,6 +250,10 @@ __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, V
     // (positions are clamped to [0,1]), so one comparison per bound suffices.
     if (!(lo[0] <= p[0] && p[0] < hi[0] && lo[1] <= p[1] && p[1] < hi[1] && lo[2] <= p[2] && p[2] < hi[2])) {
       e = find_element<LK>(s, p);
+      if (e < 0) {           // corrupt look-up structure: the visitor reports it
+        vis.corrupt(ts);
+        break;
+      }
       const float2* b2 = reinterpret_cast<const float2*>(s.box + 6 * (int64_t)e);
       const float2 b01 = b2[0], b23 = b2[1], b45 = b2[2];
       lo[0] = b01.x; lo[1] = b01.y; lo[2] = b23.x;
@@ -346,6 +350,8 @@ __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, V
 struct Composite {
   float C[3] = {0.0f, 0.0f, 0.0f};
   float T = 1.0f;
+  bool bad = false;          // the look-up met a corrupt reference
+  __device__ inline void corrupt(float) { bad = true; }
   __device__ inline float opacity(const SceneK& s, float alpha, float ds) const {
     return opacity_of(alpha, ds * s.inv_xi);
   }
@@ -377,6 +383,16 @@ struct TraceVisitor : Composite {
     }
     ++k;
     return Composite::sample<P>(s, sm);
+  }
+  // the sample whose look-up failed is recorded with element -1
+  __device__ inline void corrupt(float t) {
+    bad = true;
+    if (k < max_out) {
+      t_out[k] = t;
+      e_out[k] = kBadRef;
+      ds_out[k] = 0.0f;
+    }
+    ++k;
   }
 };
 
@@ -433,7 +449,7 @@ __device__ __forceinline__ void render_tile(const SceneK& s, const ViewsK& vk, f
     __device__ inline void finish(int k) { n = k; }
   } vis;
   if (r.hit) march<P, NCOMP, CT, MODE, COLOR, LK, SH>(s, r, lut, vis);
-  rgba[o] = make_float4(vis.C[0], vis.C[1], vis.C[2], 1.0f - vis.T);
+  rgba[o] = vis.bad ? make_float4(NAN, NAN, NAN, NAN) : make_float4(vis.C[0], vis.C[1], vis.C[2], 1.0f - vis.T);
   if (nsamples) nsamples[o] = (uint32_t)vis.n;
 }
 
@@ -601,12 +617,16 @@ struct Adjoint : Composite {
     const float w = T * a;
     float Cn[3];
     for (int ch = 0; ch < 3; ++ch) Cn[ch] = fmaf(w, sm.csrc[ch], C[ch]);
+    // om = 0: the opacity rounded to 1, T becomes 0 and the march ends at
+    // this sample; nothing follows it (suffix 0, later transmittance 1), and
+    // g_a only reaches the table through da/dalpha, which has the factor om.
     const float om = 1.0f - a;
-    float g_a = gA * Tfin / om;
+    const bool live = om > 0.0f;
+    float g_a = live ? gA * Tfin / om : gA * T;
     float g_x[4];
     for (int ch = 0; ch < 3; ++ch) {
       g_x[ch] = gC[ch] * w;
-      g_a = fmaf(gC[ch], T * sm.csrc[ch] - (Cfin[ch] - Cn[ch]) / om, g_a);
+      g_a = fmaf(gC[ch], T * sm.csrc[ch] - (live ? (Cfin[ch] - Cn[ch]) / om : 0.0f), g_a);
     }
     const float r = sm.ds * s.inv_xi;
     g_x[3] = sm.clamped ? 0.0f : g_a * r * om / (1.0f - sm.alpha);
@@ -927,7 +947,7 @@ LR_API lr_status lr_lookup(const uint32_t* heads, const lr_kdnode* nodes, int64_
   for (int d = 0; d < 3; ++d)
     if (!lrvr::is_pow2(blocks[d]) || blocks[d] > 512) return fail(LR_ENOTPOW2, "lr_lookup: blocks must be powers of two <= 512");
   if (n == 0) return LR_OK;
-  if (n > ((int64_t)1 << 40)) return fail(LR_EINVAL, "lr_lookup: too many points");
+  if (n > (int64_t)0x7fffffff * 256) return fail(LR_EINVAL, "lr_lookup: too many points (at most 2^31-1 workgroups of 256)");
   const int64_t nblk = (n + 255) / 256;
   hipLaunchKernelGGL(lookup_kernel, dim3((unsigned)nblk), dim3(256), 0, static_cast<hipStream_t>(stream), heads, nodes,
                      n_nodes, n_elem, blocks[0], blocks[1], blocks[2], points, n, elem_out);
@@ -986,7 +1006,7 @@ LR_API lr_status lr_lookup_octree(const uint32_t* root, const uint32_t* nodes, i
   if (n_elem <= 0 || n_elem >= (int64_t)LR_LEAF || n_nodes >= (int64_t)LR_LEAF)
     return fail(LR_EINVAL, "lr_lookup_octree: bad n_elem / n_nodes");
   if (n == 0) return LR_OK;
-  if (n > ((int64_t)1 << 40)) return fail(LR_EINVAL, "lr_lookup_octree: too many points");
+  if (n > (int64_t)0x7fffffff * 256) return fail(LR_EINVAL, "lr_lookup_octree: too many points (at most 2^31-1 workgroups of 256)");
   const int64_t nblk = (n + 255) / 256;
   hipLaunchKernelGGL(lookup_octree_kernel, dim3((unsigned)nblk), dim3(256), 0, static_cast<hipStream_t>(stream), root,
                      nodes, n_nodes, n_elem, points, n, elem_out);

@@ -142,6 +142,7 @@ struct Field {
   float c[NB];        // component q of the cached element's block
   int q = 0;          // component of this lane
   int lane0 = 0;      // first lane of the group
+  bool bad = false;   // a look-up met a corrupt reference
 
   __device__ inline void load_component(const StreamK& k, int32_t e) {
     // Component q starts at float q * NB of the row, not always 16-byte
@@ -180,6 +181,11 @@ struct Field {
                             ? octree_lookup(k.heads, static_cast<const uint32_t*>(k.nodes), k.n_nodes, k.n_elem, p)
                             : forest_lookup(k.heads, static_cast<const lr_kdnode*>(k.nodes), k.n_nodes, k.n_elem,
                                             k.bx, k.by, k.bz, k.fbx, k.fby, k.fbz, p);
+      if (e < 0) {           // corrupt look-up structure: the value is NaN and the line ends
+        bad = true;
+        for (int a = 0; a < 3; ++a) f[a] = (R)NAN;
+        return;
+      }
       const float* b = k.box + 6 * (int64_t)e;
       for (int a = 0; a < 3; ++a) {
         lo[a] = b[a];
@@ -257,6 +263,7 @@ __global__ __launch_bounds__(64) void stream_kernel(const StreamK k) {
         }
         fld.template at<R>(k, y, kk[i]);
       }
+      if (fld.bad) break;
       R err2 = 0;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -282,6 +289,7 @@ __global__ __launch_bounds__(64) void stream_kernel(const StreamK k) {
       h = h * (fac > (R)0.2 ? fac : (R)0.2);
       h = h > (R)1e-14 ? h : (R)1e-14;
     }
+    if (fld.bad) break;
     bool in = true;
     for (int a = 0; a < 3; ++a) in = in && xn[a] >= 0 && xn[a] <= 1;
     if (!in) break;
@@ -294,7 +302,9 @@ __global__ __launch_bounds__(64) void stream_kernel(const StreamK k) {
   if (!writer) return;
   if (k.count) k.count[j] = n;
   for (int32_t i = n; i < k.max_samples; ++i) {
-    out[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    // after a line ended at a corrupt look-up structure, its next entry is NaN
+    const float z = (fld.bad && i == n) ? NAN : 0.0f;
+    out[i] = make_float4(z, z, z, 0.0f);
     if (tout) tout[i] = 0.0;
   }
 }

@@ -115,6 +115,7 @@ class Server:
         arrived = deque()
         ready = deque()            # admitted: (index, offset)
         inflight = []              # (event, stream_idx, [(index, offset)])
+        copying = []               # (event, [(index, offset)]): images being copied out
         stream_busy = [0] * len(self.streams)
         dev = self.scene.volume.device
         start = torch.cuda.Event(enable_timing=True)
@@ -168,15 +169,33 @@ class Server:
                     t_ms = start.elapsed_time(ev)
                     for k, off in batch:
                         recs[k].done_ms = t_ms
-                        if keep_images:
-                            recs[k].image = self.arena.buf[off:off + recs[k].pixels].clone()
-                        self.arena.release(off, recs[k].pixels)
                         done += 1
+                    if keep_images:
+                        # copy out on the launch's own stream; the regions are
+                        # reused only once the copies have completed
+                        with torch.cuda.stream(self.streams[si]):
+                            for k, off in batch:
+                                recs[k].image = self.arena.buf[off:off + recs[k].pixels].clone()
+                            copied = torch.cuda.Event()
+                            copied.record(self.streams[si])
+                        copying.append((copied, batch))
+                    else:
+                        for k, off in batch:
+                            self.arena.release(off, recs[k].pixels)
                     stream_busy[si] -= 1
                     progressed = True
                 else:
                     still.append((ev, si, batch))
             inflight = still
+            waiting = []
+            for copied, batch in copying:
+                if copied.query():
+                    for k, off in batch:
+                        self.arena.release(off, recs[k].pixels)
+                    progressed = True
+                else:
+                    waiting.append((copied, batch))
+            copying = waiting
             if not progressed:
                 time.sleep(5e-5)
         torch.cuda.synchronize(dev)

@@ -1,7 +1,7 @@
-// Host-side builders of the C ABI (support CSR, k-d forest, octree) run
+// Host-side builders of the C ABI (support CSR, k-d forest, octree) and the
+// look-up descents the kernels run (lookup.h, compiled here for the host) run
 // under AddressSanitizer and UndefinedBehaviorSanitizer.  Built by
-// tests/test_host_sanitize.py with g++ from the library's host sources only
-// (no device code).  Input file: int32 p[3], int64 n_bspl, int32 kstride,
+// tests/test_host_sanitize.py with g++ from the library's host sources only.  Input file: int32 p[3], int64 n_bspl, int32 kstride,
 // double knots[n_bspl][3][kstride], int64 n_elem, double elem_box[n_elem][6],
 // int32 dyadic.  Prints one line per check and exits non-zero on a failure.
 #include <cmath>
@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "lrvr.h"
+#include "../paper_1707_01170_amd/csrc/lookup.h"
 
 namespace {
 
@@ -71,6 +72,84 @@ int64_t octree_find(uint32_t root, const std::vector<uint32_t>& nodes, const dou
   return r & ~LR_LEAF;
 }
 
+// Points of the look-up checks: element centres, lower corners, upper corners
+// (in [0,1]) and face centres, as FP32 values.
+std::vector<float> probe_points(const std::vector<double>& box, int64_t n_elem) {
+  std::vector<float> pts;
+  for (int64_t e = 0; e < n_elem; ++e) {
+    const double* b = &box[6 * e];
+    for (int k = 0; k < 5; ++k)
+      for (int a = 0; a < 3; ++a) {
+        const double m = 0.5 * (b[a] + b[3 + a]);
+        const double v = k == 0 ? m : k == 1 ? b[a] : k == 2 ? b[3 + a] : (k == 3 ? (a == 0 ? b[0] : m) : (a == 1 ? b[4] : m));
+        pts.push_back((float)v);
+      }
+  }
+  return pts;
+}
+
+// The kernels' descent (lookup.h) on the exported arrays: every probe point
+// finds the element holding it, and references made corrupt (a node index
+// beyond the nodes, an element id beyond the elements, a node that is its
+// own child) give kBadRef without reading outside the arrays.
+void check_kernel_forest(const std::vector<uint32_t>& heads, std::vector<lr_kdnode> nodes, const int32_t blk[3],
+                         const std::vector<double>& box, int64_t n_elem, const char* what) {
+  const std::vector<float> pts = probe_points(box, n_elem);
+  const int64_t nn = (int64_t)nodes.size();
+  const lr_kdnode* np = nn ? nodes.data() : nullptr;
+  bool ok = true;
+  for (size_t i = 0; i < pts.size() && ok; i += 3) {
+    const float* p = &pts[i];
+    const int32_t e = lrvr::forest_lookup(heads.data(), np, nn, n_elem, blk[0], blk[1], blk[2], (float)blk[0],
+                                          (float)blk[1], (float)blk[2], p);
+    const double x[3] = {p[0], p[1], p[2]};
+    ok = e >= 0 && e < n_elem && contains(&box[6 * e], x) && e == forest_find(heads, nodes, blk, x);
+  }
+  char msg[192];
+  std::snprintf(msg, sizeof msg, "%s: the kernels' descent finds the element of every probe point", what);
+  check(ok, msg);
+  if (nn == 0) return;
+  // corrupt references: count points whose descent reports kBadRef
+  auto bad_count = [&](const std::vector<lr_kdnode>& nd, int64_t n_el) {
+    int64_t n = 0;
+    for (size_t i = 0; i < pts.size(); i += 3)
+      n += lrvr::forest_lookup(heads.data(), nd.data(), nn, n_el, blk[0], blk[1], blk[2], (float)blk[0],
+                               (float)blk[1], (float)blk[2], &pts[i]) == lrvr::kBadRef;
+    return n;
+  };
+  std::vector<lr_kdnode> c1(nodes), c2(nodes);
+  c1[0].lo = (uint32_t)nn + 5;          // node index beyond the node array
+  c1[0].hi = 0xfffffffu;
+  c2[0].lo = 0;                         // node 0 is its own child: no leaf is ever reached
+  c2[0].hi = 0;
+  const bool caught = bad_count(c1, n_elem) > 0 && bad_count(c2, n_elem) > 0 && bad_count(nodes, 1) > 0;
+  std::snprintf(msg, sizeof msg, "%s: corrupt references are reported, not followed", what);
+  check(caught, msg);
+}
+
+void check_kernel_octree(uint32_t root, std::vector<uint32_t> nodes, const std::vector<double>& box, int64_t n_elem) {
+  const std::vector<float> pts = probe_points(box, n_elem);
+  const int64_t nn = (int64_t)nodes.size() / 8;
+  bool ok = true;
+  for (size_t i = 0; i < pts.size() && ok; i += 3) {
+    const float* p = &pts[i];
+    const int32_t e = lrvr::octree_lookup(&root, nn ? nodes.data() : nullptr, nn, n_elem, p);
+    const double x[3] = {p[0], p[1], p[2]};
+    ok = e >= 0 && e < n_elem && contains(&box[6 * e], x) && e == octree_find(root, nodes, x);
+  }
+  check(ok, "octree: the kernels' descent finds the element of every probe point");
+  if (nn == 0) return;
+  int64_t n_bad = 0;
+  std::vector<uint32_t> c1(nodes);
+  for (int k = 0; k < 8; ++k) c1[k] = (uint32_t)nn + 3;          // children beyond the nodes
+  for (size_t i = 0; i < pts.size(); i += 3) n_bad += lrvr::octree_lookup(&root, c1.data(), nn, n_elem, &pts[i]) < 0;
+  std::vector<uint32_t> c2(nodes);
+  for (int k = 0; k < 8; ++k) c2[k] = 0;                           // root is its own child
+  int64_t n_loop = 0;
+  for (size_t i = 0; i < pts.size(); i += 3) n_loop += lrvr::octree_lookup(&root, c2.data(), nn, n_elem, &pts[i]) < 0;
+  check(n_bad > 0 && n_loop > 0, "octree: corrupt references are reported, not followed");
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
@@ -124,6 +203,8 @@ int main(int argc, char** argv) {
     }
     std::snprintf(what, sizeof what, "forest %dx%dx%d: every element centre finds its element", blk[0], blk[1], blk[2]);
     check(found, what);
+    std::snprintf(what, sizeof what, "forest %dx%dx%d", blk[0], blk[1], blk[2]);
+    check_kernel_forest(heads, nodes, blk, box, n_elem, what);
     lr_forest_free(h);
   }
 
@@ -144,6 +225,7 @@ int main(int argc, char** argv) {
         found = g >= 0 && g < n_elem && contains(&box[6 * g], c);
       }
       check(found, "octree: every element centre finds its element");
+      check_kernel_octree(root, nodes, box, n_elem);
       lr_octree_free(o);
     }
   }

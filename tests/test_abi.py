@@ -33,6 +33,46 @@ def test_exports_every_declared_symbol():
     assert lib.lr_version() >= 100
 
 
+def test_build_id_matches_sources():
+    """The loaded library was built from the sources in the tree."""
+    from paper_1707_01170_amd import _build
+    assert L.lib().lr_build_id().decode() == _build.source_digest()
+
+
+def test_forest_device_size_query():
+    """lr_build_forest_device, phase 1 (no device buffers): the sizes and
+    statistics of the host build, and its argument checks; nothing touches a
+    device."""
+    lib = L.lib()
+    s = lrgen.small_random(p=(2, 2, 2), n=(4, 4, 4), n_ref=30, seed=3)
+    eb = np.ascontiguousarray(s.elem_box, dtype=np.float32)
+    for blocks in (1, 4):
+        ref = P.Forest.build(s.elem_box, blocks)
+        b = np.array([blocks] * 3, np.int32)
+        nn = ctypes.c_int64(-1)
+        st = L.ForestStats()
+        assert lib.lr_build_forest_device(eb.ctypes.data, eb.shape[0], b.ctypes.data, None, None, 0,
+                                          ctypes.byref(nn), ctypes.byref(st), None) == L.LR_OK
+        assert nn.value == ref.stats["n_nodes"] == st.n_nodes and st.n_heads == blocks ** 3
+        assert st.max_depth == ref.stats["max_depth"]
+    f = ctypes.c_void_p(0x1000)
+    b = np.array([4, 4, 4], np.int32)
+    assert lib.lr_build_forest_device(eb.ctypes.data, eb.shape[0], b.ctypes.data, f, None, 5, None, None,
+                                      None) == L.LR_EINVAL
+    assert lib.lr_build_forest_device(eb.ctypes.data, eb.shape[0], b.ctypes.data, None, f, 5, None, None,
+                                      None) == L.LR_EINVAL
+    b = np.array([4, 3, 4], np.int32)
+    assert lib.lr_build_forest_device(eb.ctypes.data, eb.shape[0], b.ctypes.data, None, None, 0, None, None,
+                                      None) == L.LR_ENOTPOW2
+    b = np.array([1, 1, 1], np.int32)
+    small = ctypes.c_int64()
+    lib.lr_build_forest_device(eb.ctypes.data, eb.shape[0], b.ctypes.data, None, None, 0, ctypes.byref(small),
+                               None, None)
+    assert small.value > 1
+    assert lib.lr_build_forest_device(eb.ctypes.data, eb.shape[0], b.ctypes.data, f, f, small.value - 1, None, None,
+                                      None) == L.LR_ECAPACITY
+
+
 def test_struct_sizes():
     assert ctypes.sizeof(L.ViewC) == 80 and ctypes.sizeof(L.SceneC) == 144
     assert P.bezier_stride((2, 2, 2), 1, L.LR_F32) == 28
@@ -242,6 +282,10 @@ def test_lookup_and_extract_validate_first():
     b = np.array([4, 4, 4], np.int32)
     assert lib.lr_lookup(f, f, 1, b.ctypes.data, 10, f, 0, f, None) == L.LR_OK       # empty batch
     assert lib.lr_lookup(f, f, 1, b.ctypes.data, 0, f, 5, f, None) == L.LR_EINVAL
+    # the grid of 256-point workgroups must fit 2^31 - 1 workgroups
+    assert lib.lr_lookup(f, f, 1, b.ctypes.data, 10, f, 0x7fffffff * 256 + 1, f, None) == L.LR_EINVAL
+    assert lib.lr_lookup_octree(f, f, 1, 10, f, 0x7fffffff * 256 + 1, f, None) == L.LR_EINVAL
+    assert b"too many points" in lib.lr_last_error()
     s = L.LRSplineDev()
     s.p[:] = (2, 2, 2)
     s.ncomp, s.kstride, s.n_bspl, s.n_elem = 1, 4, 10, 5

@@ -15,11 +15,31 @@ import bench  # noqa: E402
 
 
 def test_flops_per_sample_counts():
-    # (2,2,2) vector field: 6 + 6 + 15 + 2*(27+9+3)*3 + 11 + 13 + 13
-    assert bench.flops_per_sample(2, 3) == 298
-    # (2,2,2) scalar and (3,3,3) scalar
-    assert bench.flops_per_sample(2, 1) == 6 + 6 + 15 + 78 + 11 + 13
-    assert bench.flops_per_sample(3, 1) == 6 + 6 + 30 + 2 * (64 + 16 + 4) + 11 + 13
+    # the hot-path scope table's per-sample totals: 133 (degree-2 scalar),
+    # 238 (degree-3 scalar), 325 (degree-2 3-vector)
+    assert bench.flops_per_sample(2, 1) == 15 + 2 * (27 + 9 + 3) + 40 == 133
+    assert bench.flops_per_sample(3, 1) == 30 + 2 * (64 + 16 + 4) + 40 == 238
+    assert bench.flops_per_sample(2, 3) == 15 + 2 * (27 + 9 + 3) * 3 + 40 + 36 == 325
+    # the adjoint's scatter of dv/dC_j = B_j(u): 2 (p+1)^3 + 2 (p+1)^2
+    for p in (1, 2, 3):
+        assert bench.ADJOINT_EXTRA_FLOPS[p] == 70 + 2 * (p + 1) ** 3 + 2 * (p + 1) ** 2
+
+
+def test_accuracy_is_peak_relative():
+    import numpy as np
+    import torch
+
+    class V:
+        width, height = 4, 3
+    ref = np.zeros((3, 4), np.float64)
+    ref[:, 3] = 0.5
+    ii, jj = np.array([0, 3, 2]), np.array([0, 1, 2])
+    frame = torch.zeros((12, 4))
+    frame[jj * 4 + ii] = torch.from_numpy(ref).float()
+    frame[1 * 4 + 3, 3] = 0.51
+    a = bench.accuracy(frame, V, (ii, jj, ref))
+    assert abs(a["max"] - 0.01 / 0.5) < 1e-6
+    assert abs(a["rms"] - np.sqrt(0.01 ** 2 / 12) / 0.5) < 1e-6
 
 
 def _copy_sources(dst):

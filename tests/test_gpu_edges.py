@@ -129,3 +129,38 @@ def test_fp16_blocks_same_schedule():
     for k in range(pix.shape[0]):
         n = min(c16[k], c32[k])
         assert np.array_equal(a[0][k, :n].cpu(), b[0][k, :n].cpu()) and np.array_equal(a[1][k, :n].cpu(), b[1][k, :n].cpu())
+
+
+def test_corrupt_forest_is_reported():
+    """A forest whose references point past its nodes or elements: the
+    descent's own bounds checks report it (element -1 from lr_lookup, NaN
+    pixels from lr_render) instead of reading past the arrays, and points and
+    rays that never meet the corrupt references are unaffected."""
+    import paper_1707_01170_amd as P
+    from paper_1707_01170_amd import _lib as L
+    say("[gpu] corrupt forest")
+    s = lrgen.small_random(p=(2, 2, 2), n=(4, 4, 4), n_ref=30, seed=44)
+    wl = _wl(s, [lrgen.sphere_view([0.2, -0.9, 0.4], 32, 24)])
+    vol = P.Volume(s, blocks=1)
+    assert vol.n_nodes > 8
+    sc = P.Scene(vol, P.RenderParams.of(wl))
+    good, _, _ = P.render(sc, wl.views)
+    pts = torch.from_numpy(np.random.default_rng(3).random((4096, 3)).astype(np.float32))
+    ids_good = P.lookup(vol, pts).cpu().numpy()
+    nodes = vol.nodes.clone()
+    nodes[1, 0] = vol.n_nodes + 5                                         # a node index past the nodes
+    nodes[2, 1] = np.int32(np.uint32(L.LR_LEAF | (vol.n_elem + 7)).view(np.int32))   # an element past the elements
+    saved = vol.nodes
+    vol.nodes = nodes
+    try:
+        ids = P.lookup(vol, pts).cpu().numpy()
+        bad, _, _ = P.render(sc, wl.views)
+        torch.cuda.synchronize()
+    finally:
+        vol.nodes = saved
+    bad, good = bad.cpu().numpy(), good.cpu().numpy()
+    hit = ids == -1
+    assert hit.any() and np.array_equal(ids[~hit], ids_good[~hit])
+    nan = np.isnan(bad).any(axis=1)
+    assert nan.any() and np.array_equal(bad[~nan], good[~nan])
+    say("corrupt forest: %d of %d points report -1, %d of %d pixels NaN" % (hit.sum(), hit.size, nan.sum(), nan.size))

@@ -42,6 +42,22 @@ def test_lookup_bit_exact(name, blocks):
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("name,blocks", [("scalar20k", 16), ("scalar20k", 1), ("vortex200k", 256)])
+def test_forest_written_to_device(name, blocks):
+    """lr_build_forest_device (size query, then build and copy on the stream)
+    writes the same heads and nodes as the host build's export, and the
+    look-up through them is the brute-force scan's."""
+    import paper_1707_01170_amd as P
+    say("[gpu] forest to device", name, blocks)
+    wl = workload(name)
+    heads, nodes, stats = P.build_forest_device(wl.spline.elem_box, blocks)
+    torch.cuda.synchronize()
+    ref = P.Forest.build(wl.spline.elem_box, blocks)
+    assert np.array_equal(heads.cpu().numpy().view(np.uint32), ref.heads)
+    assert np.array_equal(nodes.cpu().numpy().view(np.uint32), ref.nodes)
+    assert stats["n_nodes"] == ref.stats["n_nodes"] and stats["max_depth"] == ref.stats["max_depth"]
+
+
 # ---------------------------------------------------------------- Sec. 3.2.3 extraction
 def _small_vector():
     s = lrgen.small_random(p=(2, 2, 2), n=(4, 4, 4), n_ref=40, seed=31, ncomp=3)
@@ -225,7 +241,7 @@ def test_constant_field_closed_form():
     assert np.abs(rgba[:, :3] - alpha[:, None] * lut[k, :3]).max() < 2e-5
 
 
-@pytest.mark.parametrize("name", ["blobs50k", "scalar20k"])
+@pytest.mark.parametrize("name", ["blobs50k", "scalar20k", "vortex200k"])
 def test_fp16_storage(name):
     """FP16 Bezier storage with FP32 arithmetic: error stated, sanity-bounded."""
     say("[gpu] fp16", name)
@@ -239,6 +255,24 @@ def test_fp16_storage(name):
     e16, r16 = peak_rel(a, ref)
     e32, r32 = peak_rel(b, ref)
     say("%s fp16 peak-rel %.3e rms %.3e | fp32 %.3e rms %.3e" % (name, e16, r16, e32, r32))
+    assert e16 <= TOL_F16 and e32 <= TOL_F32
+
+
+def test_fp16_storage_benchmark_launch_sampled():
+    """The timed 1080p launch of the vector volume (forest 256^3) from FP16
+    blocks, on seeded pixels and one tile, against the oracle; the FP32 launch
+    on the same pixels beside it."""
+    say("[gpu] fp16 1080p vector launch")
+    wl, sc16 = scene("vortex200k", blocks=256, dtype="f16")
+    _, sc32 = scene("vortex200k", blocks=256)
+    view = wl.views[0]
+    a, _, _ = _render(sc16, [view])
+    b, _, _ = _render(sc32, [view])
+    ii, jj = sample_pixels(view, 1024, seed=8, tile=24)
+    ref, _, _ = oracle_render("vortex200k", view, ii, jj)
+    e16, r16 = peak_rel(a[jj * view.width + ii], ref)
+    e32, r32 = peak_rel(b[jj * view.width + ii], ref)
+    say("vortex200k 1080p: fp16 peak-rel %.3e rms %.3e | fp32 %.3e rms %.3e" % (e16, r16, e32, r32))
     assert e16 <= TOL_F16 and e32 <= TOL_F32
 
 

@@ -29,15 +29,20 @@ def _stream(n, seed, sizes=(40, 64, 96, 128, 200)):
             for k in range(n)]
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f16"])
-def test_results_identical_alone_and_in_the_mix(dtype):
+@pytest.mark.parametrize("dtype,time_scale", [("f32", 1.0), ("f16", 1.0), ("f32", 0.0), ("f16", 0.05)])
+def test_results_identical_alone_and_in_the_mix(dtype, time_scale):
+    """Each request's image is the same bits alone and batched with others;
+    time_scale compresses the arrivals (0: all at once), so that requests
+    queue and launches carry several views."""
     from paper_1707_01170_amd.serve import Server, render_alone
-    say("[gpu] serve mix", dtype)
+    say("[gpu] serve mix", dtype, time_scale)
     _, sc = scene("blobs50k", dtype=dtype)
     reqs = _stream(60, 1)
     srv = Server(sc, budget_bytes=16 * 200 * 200 * 6, n_streams=3)
-    st = srv.run(reqs, keep_images=True)
+    st = srv.run(reqs, keep_images=True, time_scale=time_scale)
     assert st.n == 60 and st.launches < 60 and st.max_inflight >= 1
+    if time_scale == 0.0:
+        assert st.mean_views_per_launch > 2.0
     for r in st.results:
         alone = render_alone(sc, reqs[r.index].view)
         assert torch.equal(r.image, alone), r.index

@@ -558,6 +558,41 @@ def test_gradient_matches_finite_differences():
             assert abs(fd - gl[row, ch]) <= 1e-5 * max(1.0, abs(fd))
 
 
+def test_gradient_where_opacity_saturates():
+    """A short standard length xi makes a = 1 - (1 - alpha)^(ds/xi) round to
+    exactly 1 in FP64 for clamped samples (R16); the reverse mode stays finite
+    and equals central differences there (Alg. 2 differentiated)."""
+    s = lrgen.small_random(p=(2, 2, 2), n=(4, 4, 4), n_ref=30, seed=61)
+    rng = np.random.default_rng(62)
+    w = lrgen.Workload("sat", s, lrgen.default_lut(), 0.0, 0.6, "adaptive", 0, "lut",
+                       [lrgen.sphere_view([0.3, 0.8, -0.5], 13, 10)], xi=0.004)
+    tgt = s.with_coef(rng.random(s.coef.shape))
+    ev = LREvaluator(s)
+    C = obez.extract(s, ev)
+    Ct = obez.extract(tgt, LREvaluator(tgt))
+    view = w.views[0]
+    ii, jj = ocam.pixel_grid(view)
+    ei = ElementIndex(s.elem_box)
+    target, _, _ = orr.render_view(w, view, orr.BezierField(s, Ct), eidx=ei)
+    rgba, ns, recs = ograd.forward_records(w, view, C, ei)
+    assert sum(int(np.sum(r["a"] == 1.0)) for r in recs) > 0
+    gb, gl = ograd.backward(w, C, recs, ii.size, ograd.l2_grad(rgba, target))
+    assert np.isfinite(gb).all() and np.isfinite(gl).all()
+    hit_e = np.unique(np.concatenate([r["e"] for r in recs]))
+    n_checked = 0
+    for e in rng.choice(hit_e, 40, replace=False):
+        j = int(rng.integers(0, 27))
+        if ograd.kink_samples(w, recs, int(e), j, 1e-3):
+            continue
+        fd = ograd.fd_coefficient(w, view, C, ei, ii, jj, target, int(e), j, h=1e-3)
+        assert abs(fd - gb[e, 0, j]) <= 1e-3 * max(abs(fd), 1e-3 * np.abs(gb).max())
+        n_checked += 1
+    assert n_checked >= 12
+    for row in np.argsort(-np.abs(gl).sum(1))[:3]:
+        fd = ograd.fd_lut(w, view, C, ei, ii, jj, target, int(row), 0, h=1e-3)
+        assert abs(fd - gl[row, 0]) <= 1e-5 * max(1.0, abs(fd))
+
+
 # ---------------------------------------------------------------- adjoint of the change of basis
 def test_extraction_adjoint_brute_force():
     """Transpose of the explicit extraction matrix, built column by column by
