@@ -6,7 +6,11 @@ T_i = prod_{j<i} (1 - a_i) the transmittance before sample i,
 a_i = 1 - (1 - alpha_i)^(ds_i/xi), and c_i = T_i a_i C_src,i its contribution:
   C = sum_i c_i,   alpha = 1 - prod_i (1 - a_i)
   dC/dC_src,i = T_i a_i
-  dC/da_i     = T_i C_src,i - (sum_{k>i} c_k) / (1 - a_i)
+  dC/da_i     = T_i (C_src,i - S_i),  S_i = sum_{k>i} prod_{i<j<k} (1 - a_j) a_k C_src,k
+                (the radiance behind sample i seen from just behind it, summed
+                back to front: S_i = a_{i+1} C_src,i+1 + (1 - a_{i+1}) S_{i+1};
+                this equals (sum_{k>i} c_k) / (1 - a_i) without dividing, so it
+                also holds where a_i rounds to 1)
   dalpha/da_i = prod_{j != i} (1 - a_j)
   da_i/dalpha_i = (ds_i/xi) (1 - alpha_i)^(ds_i/xi - 1)   (0 where alpha is clamped)
 then through the linear interpolation of the table (weights 1-w, w on rows i0,
@@ -44,18 +48,18 @@ def backward(wl, C, recs, R: int, g_rgba: np.ndarray):
         a[k, r["idx"]] = r["a"]
         Tb[k, r["idx"]] = r["Tb"]
         cs[k, r["idx"]] = r["csrc"]
-    contrib = (Tb * a)[:, :, None] * cs
-    suffix_incl = np.cumsum(contrib[::-1], axis=0)[::-1]
-    after = suffix_incl - contrib                               # sum_{k>i} c_k
     one_m_a = 1.0 - a
+    # S_i, back to front (records without a sample for a ray have a = 0, C_src = 0)
+    S = np.zeros((K, R, 3))
+    for k in range(K - 2, -1, -1):
+        S[k] = a[k + 1][:, None] * cs[k + 1] + one_m_a[k + 1][:, None] * S[k + 1]
     # prod_{j>i} (1 - a_j)
     rev = np.cumprod(one_m_a[::-1], axis=0)[::-1]
     prod_after = np.concatenate([rev[1:], np.ones((1, R))], axis=0)
     gC = g_rgba[:, :3]
     gA = g_rgba[:, 3]
     g_csrc = (Tb * a)[:, :, None] * gC[None]
-    g_a = (gC[None] * (Tb[:, :, None] * cs - after / one_m_a[:, :, None])).sum(-1) \
-        + gA[None] * Tb * prod_after
+    g_a = (gC[None] * (Tb[:, :, None] * (cs - S))).sum(-1) + gA[None] * Tb * prod_after
     gbez = np.zeros_like(C)
     glut = np.zeros((256, 4))
     for k, r in enumerate(recs):
