@@ -248,7 +248,8 @@ __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, V
     position(r, ts, p);
     // Half-open containment; hi is stored as 2 where the box is closed at 1
     // (positions are clamped to [0,1]), so one comparison per bound suffices.
-    if (!(lo[0] <= p[0] && p[0] < hi[0] && lo[1] <= p[1] && p[1] < hi[1] && lo[2] <= p[2] && p[2] < hi[2])) {
+    const bool need = !(lo[0] <= p[0] && p[0] < hi[0] && lo[1] <= p[1] && p[1] < hi[1] && lo[2] <= p[2] && p[2] < hi[2]);
+    if (need) {
       e = find_element<LK>(s, p);
       if (e < 0) {           // corrupt look-up structure: the visitor reports it
         vis.corrupt(ts);
@@ -262,7 +263,7 @@ __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, V
       ds_e = side * step_scale;
       for (int a = 0; a < 3; ++a) inv[a] = __builtin_amdgcn_rcpf(hi[a] - lo[a]);
       for (int a = 0; a < 3; ++a) hi[a] = hi[a] == 1.0f ? 2.0f : hi[a];
-      Coef<NCF, CT>::load(s.bez, s.stride, e, c);
+      CF::load(s.bez, s.stride, e, c);
     }
     Sample<P> sm;
     sm.e = e;
@@ -531,26 +532,49 @@ __global__ void lookup_octree_kernel(const uint32_t* __restrict__ root, const ui
 // Bezier coefficients of the sample's element (dv/dC_j = B_j(u)).
 //
 // Accumulation: a lane sums the gradient of consecutive samples of one
-// element in registers; on element change it adds the sum into a workgroup
-// hash table in LDS (the 64 rays of an 8x8 tile share most elements):
-// a slot is claimed for an element by compare-and-swap on its tag when the
-// lane enters the element (its result is read when the lane leaves it; on a
-// collision the lane probes on then, linearly), values are added with LDS
-// atomics, and the table is written to
-// global memory with atomics once, when the workgroup ends (if it fills, the
-// lane adds to global memory directly).  Table gradients are summed in
-// registers while the table row stays the same, then added into an LDS copy
-// of the table.  Both LDS tables accumulate in FP64: on gfx950 an LDS FP64
+// element in registers; on element change it adds the sums into a small hash
+// table in LDS (the 64 rays of an 8x8 tile share most elements): a slot is
+// claimed for an element by compare-and-swap on its tag when the lane enters
+// the element (its result is read when the lane leaves it; on a collision the
+// lane probes on then, linearly), and values are added with LDS FP64 atomics.
+// The table has four copies, lane l using copy l mod 4, so that neighbouring
+// rays leaving the same element in the same step add to different addresses
+// (same-address atomics of one instruction are serialised).  When a lane
+// finds its copy full, the wave writes the whole table to global memory with
+// atomics, clears it, claims the slots of its current elements again and goes
+// on; at the end the workgroup writes what is left.  The table is small so
+// that several waves share a SIMD: at one wave per SIMD the ray march's load
+// latencies are exposed.  Table-row gradients are summed in registers while
+// the row stays the same, then added into an LDS copy of the table (FP64).
+// The transfer table itself is read from global memory (L1-resident): an LDS
+// read would wait behind the wave's queued atomics.  On gfx950 an LDS FP64
 // atomic add to distinct addresses issues ~20x faster than an FP32 one
-// (measured ~10 against ~200 CU cycles per wavefront instruction), which
-// more than pays for the halved occupancy (40 KB of LDS: one wave per SIMD).
+// (measured ~11 against ~195 CU cycles per wavefront instruction).
 template <int P>
 struct GradTable {
   static constexpr int NB = (P + 1) * (P + 1) * (P + 1);
-  static constexpr int kSlots = 128;   // per workgroup (one 8x8 tile of rays)
-  static constexpr int kLog2Slots = 7;
-  static constexpr int kProbes = 16;
+  static constexpr int kLog2Slots = 3;
+  static constexpr int kSlots = 1 << kLog2Slots;   // per copy
+  static constexpr int kProbes = kSlots;
+  static constexpr int kCopies = 4;                // lane l uses copy l mod 4
 };
+
+// The active lanes write every non-zero entry of the element table to the
+// global gradient (FP32 atomics) and clear the table.  The wave's LDS
+// operations complete in order, so every tag is read before it is cleared.
+template <int NB, int S>
+__device__ inline void spill_table(float* __restrict__ gbez, int64_t stride, int32_t* htag, double* hval) {
+  const uint64_t act = __ballot(1);
+  const int na = __popcll(act);
+  const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+  for (int i = rank; i < S * NB; i += na) {
+    const int32_t t = htag[i / NB];
+    const double v = hval[i];
+    if (t >= 0 && v != 0.0) unsafeAtomicAdd(gbez + (int64_t)t * stride + (i % NB), (float)v);
+    hval[i] = 0.0;
+  }
+  for (int i = rank; i < S; i += na) htag[i] = -1;
+}
 
 template <int P>
 struct Adjoint : Composite {
@@ -584,29 +608,38 @@ struct Adjoint : Composite {
     }
   }
 
-  __device__ inline void flush_elem() {
-    if (cur < 0) return;
-    int32_t slot = -1;
-    if (claim == -1 || claim == cur) {
-      slot = (int32_t)h_cur;
-    } else {
-      uint32_t h = (h_cur + 1) & (kSlots - 1);
-      for (int probe = 1; probe < GradTable<P>::kProbes; ++probe) {
-        const int32_t t = atomicCAS(&htag[h], -1, cur);
-        if (t == -1 || t == cur) {
-          slot = (int32_t)h;
-          break;
-        }
-        h = (h + 1) & (kSlots - 1);
-      }
+  // Slot of cur: the one claimed on entry, else by linear probing; -1 if the
+  // table is full.
+  __device__ inline int32_t resolve() {
+    if (claim == -1 || claim == cur) return (int32_t)h_cur;
+    const uint32_t base = h_cur & ~(uint32_t)(kSlots - 1);
+    uint32_t h = (h_cur + 1) & (kSlots - 1);
+    for (int probe = 1; probe < GradTable<P>::kProbes; ++probe) {
+      const int32_t t = atomicCAS(&htag[base + h], -1, cur);
+      if (t == -1 || t == cur) return (int32_t)(base + h);
+      h = (h + 1) & (kSlots - 1);
     }
-    if (slot >= 0) {
-      double* v = hval + slot * NB;
+    return -1;
+  }
+
+  // Adds the sums of the element the lane leaves (cur) into the table.  Every
+  // active lane calls it (with cur < 0 if it has nothing to add), so that a
+  // full table can be spilled by the whole wave.
+  __device__ inline void deposit(bool want) {
+    int32_t ref = want ? resolve() : 0;
+    if (__ballot(want && ref < 0)) {
+      spill_table<NB, kSlots * GradTable<P>::kCopies>(gbez, stride, htag, hval);
+      if (cur >= 0) claim = atomicCAS(&htag[h_cur], -1, cur);
+      if (want) ref = resolve();
+    }
+    if (!want) return;
+    if (ref >= 0) {
+      double* v = hval + ref * NB;
 #pragma unroll
       for (int j = 0; j < NB; ++j) atomicAdd(v + j, (double)acc[j]);   // straight-line, no per-value branches
       return;
     }
-    float* out = gbez + (int64_t)cur * stride;
+    float* out = gbez + (int64_t)cur * stride;             // still no slot: straight to global memory
 #pragma unroll
     for (int j = 0; j < NB; ++j)
       if (acc[j] != 0.0f) unsafeAtomicAdd(out + j, acc[j]);
@@ -647,13 +680,15 @@ struct Adjoint : Composite {
     g_s = fmaf(g_x[2], l1.z - l0.z, g_s);
     g_s = fmaf(g_x[3], l1.w - l0.w, g_s);
     const float g_v = sm.tf.inside ? g_s * range_scale : 0.0f;
-    if (sm.e != cur) {
-      flush_elem();
+    const bool enter = sm.e != cur;
+    deposit(enter && cur >= 0);
+    if (enter) {
       cur = sm.e;
       // Claim the element's slot now; the result is first needed when the
       // lane leaves the element, so the compare-and-swap's latency is hidden
       // behind the element's samples.
-      h_cur = ((uint32_t)cur * 2654435761u) >> (32 - GradTable<P>::kLog2Slots);
+      h_cur = (((uint32_t)cur * 2654435761u) >> (32 - GradTable<P>::kLog2Slots)) +
+              (threadIdx.x & (GradTable<P>::kCopies - 1)) * kSlots;
       claim = atomicCAS(&htag[h_cur], -1, cur);
 #pragma unroll
       for (int j = 0; j < NB; ++j) acc[j] = 0.0f;
@@ -674,7 +709,10 @@ struct Adjoint : Composite {
     return T <= s.t_term;
   }
   __device__ inline void finish(int) {
-    flush_elem();
+    // A lane whose ray ended early waited here while the others marched on;
+    // if they spilled the table meanwhile, its entry claim is stale: claim again.
+    if (cur >= 0) claim = atomicCAS(&htag[h_cur], -1, cur);
+    deposit(cur >= 0);
     flush_row();
   }
 };
@@ -683,12 +721,10 @@ template <int P, int MODE, int LK>
 __global__ __launch_bounds__(kThreads) void backward_kernel(const SceneK s, const ViewsK vk, const float4* __restrict__ fwd,
                                                            const float4* __restrict__ grad, float* __restrict__ gbez,
                                                            float* __restrict__ glut) {
-  constexpr int NB = GradTable<P>::NB, S = GradTable<P>::kSlots;
-  __shared__ float4 lut[256];
+  constexpr int NB = GradTable<P>::NB, S = GradTable<P>::kSlots * GradTable<P>::kCopies;
   __shared__ double glut_s[1024];
   __shared__ int32_t htag[S];
   __shared__ double hval[S * NB];
-  for (int i = threadIdx.x; i < 256; i += kThreads) lut[i] = s.lut[i];
   for (int i = threadIdx.x; i < 1024; i += kThreads) glut_s[i] = 0.0;
   for (int i = threadIdx.x; i < S; i += kThreads) htag[i] = -1;
   for (int i = threadIdx.x; i < S * NB; i += kThreads) hval[i] = 0.0;
@@ -716,12 +752,12 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(const SceneK s, cons
       vis.htag = htag;
       vis.hval = hval;
       vis.range_scale = 255.0f * s.inv_range;
-      vis.lut = lut;
-      march<P, 1, float, MODE, LR_COLOR_LUT, LK>(s, r, lut, vis);
+      vis.lut = s.lut;
+      march<P, 1, float, MODE, LR_COLOR_LUT, LK>(s, r, s.lut, vis);
     }
   }
   __syncthreads();
-  // write the block's element sums and table gradient to global memory
+  // write what is left of the block's element sums and its table gradient
   for (int i = threadIdx.x; i < S * NB; i += kThreads) {
     const int32_t t = htag[i / NB];
     if (t >= 0 && hval[i] != 0.0) unsafeAtomicAdd(gbez + (int64_t)t * s.stride + (i % NB), (float)hval[i]);

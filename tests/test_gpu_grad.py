@@ -182,7 +182,10 @@ def test_backward_saturated_opacity():
     say("[gpu] backward saturated opacity")
     s = lrgen.small_random(p=(2, 2, 2), n=(4, 4, 4), n_ref=30, seed=61)
     views = [lrgen.sphere_view([0.3, 0.8, -0.5], 26, 20)]
-    wl = lrgen.Workload("sat", s, lrgen.default_lut(), 0.0, 0.6, "adaptive", 0, "lut", views, xi=0.004)
+    # the march stops only where the transmittance is exactly 0 (not at the
+    # default 2^-16), so that the oracle, which never stops, sees the same samples
+    wl = lrgen.Workload("sat", s, lrgen.default_lut(), 0.0, 0.6, "adaptive", 0, "lut", views, xi=0.004,
+                        term_alpha=1.0)
     C = obez.extract(s, LREvaluator(s))
     ei = ElementIndex(s.elem_box)
     ii, jj = _grid(views[0])

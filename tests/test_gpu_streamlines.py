@@ -143,12 +143,22 @@ def test_embedded_error_matches_oracle(method):
     # lines with the same number of accepted steps, point by point: the
     # accept/reject decisions and step factors come from error estimates of
     # FP32 field values (GPU) and FP64 ones (oracle)
+    # The step factors come from error estimates of FP32 (GPU) and FP64
+    # (oracle) field values, so the accepted times drift apart slightly; a
+    # point then differs from the oracle's by the distance travelled in that
+    # time difference (speed |f| times |dt|) plus the FP32 evaluation.
     equal = np.nonzero(cnt == c)[0]
-    dx = max(float(np.abs(pts[j, :c[j], :3] - X[j, :c[j]]).max()) for j in equal) if equal.size else 0.0
-    dt = max(float(np.abs(tim[j, :c[j]] - T[j, :c[j]]).max()) for j in equal) if equal.size else 0.0
-    say("embedded %s: %d of 12 lines with equal counts; point by point |dx| <= %.2e, |dt| <= %.2e"
-        % (method, equal.size, dx, dt))
-    assert equal.size >= 9 and dx <= 1e-5 and dt <= 1e-3
+    dx = dt = excess = 0.0
+    for j in equal:
+        n = c[j]
+        d = np.abs(pts[j, :n, :3] - X[j, :n]).max(axis=1)
+        tdiff = np.abs(tim[j, :n] - T[j, :n])
+        speed = np.sqrt((f(np.clip(X[j, :n], 0.0, 1.0)) ** 2).sum(axis=1))
+        dx, dt = max(dx, float(d.max())), max(dt, float(tdiff.max()))
+        excess = max(excess, float((d - 1.5 * speed * tdiff).max()))
+    say("embedded %s: %d of 12 lines with equal counts; point by point |dx| <= %.2e, |dt| <= %.2e, |dx| beyond "
+        "the time difference <= %.2e" % (method, equal.size, dx, dt, excess))
+    assert equal.size >= 9 and dt <= 1e-3 and excess <= 2e-6
     assert np.all(np.abs(T[np.arange(12), c - 1] - 0.25) < 1e-12)
     assert np.all(np.abs(tim[np.arange(12), cnt - 1] - 0.25) < 1e-12)
     assert e_gpu <= 2 * e_orc + 1e-7 and e_orc <= 2 * e_gpu + 1e-7
