@@ -385,6 +385,10 @@ def main():
     ap.add_argument("--cpu-rays", type=int, default=524288, help="rays of the oracle CPU baseline (0: skip)")
     ap.add_argument("--copy-calib", action="store_true", help="also run a plain copy of known size (counter scale)")
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false", help="skip the adjoint step timing")
+    ap.add_argument("--no-extras", dest="extras", action="store_false",
+                    help="time only the plain frame (no FP16, illuminated or streamline legs; for counter runs)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the differentiable step on the scalar volume, printed as its own JSON line")
     ap.add_argument("--stream-study", action="store_true",
                     help="also compare every RK method / step rule / precision by the error metric Eq. 7")
     ap.add_argument("--lookup-sweep", action="store_true",
@@ -396,6 +400,11 @@ def main():
         print("bench.py measures one GPU only (--gpus 1): the renderer has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.adjoint_only:
+        import torch
+        print(json.dumps({"adjoint": adjoint_step(torch.device("cuda:0"), steps=args.steps)}), flush=True)
+        return
 
     import lrgen
     log("generating workload")
@@ -453,43 +462,45 @@ def main():
         acc = {args.dtype: accuracy(out, view, oracle_pix), "rays": int(oracle_pix[0].size)}
         log("accuracy of the timed frame (%s blocks) on %d oracle rays: peak-relative max %.2e rms %.2e"
             % (args.dtype, acc["rays"], acc[args.dtype]["max"], acc[args.dtype]["rms"]))
-    # FP16 Bezier storage with FP32 arithmetic: the same frame
-    vol16 = P.Volume(wl.spline, blocks=args.blocks, dtype="f16", device=dev)
-    sc16 = P.Scene(vol16, P.RenderParams.of(wl))
-    out16 = torch.empty_like(rgba)
-    for _ in range(2):
-        P.render(sc16, views, out=out16)
-    ha, hb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ha.record(stream)
-    for _ in range(args.steps):
-        P.render(sc16, views, out=out16)
-    hb.record(stream)
-    torch.cuda.synchronize()
-    f16_ms = ha.elapsed_time(hb) / args.steps
-    f16_diff = float((out16 - rgba).abs().max() / rgba.abs().max())
-    log("FP16 blocks: %.3f ms per frame (%.2fx), peak-relative difference to FP32 %.2e" % (f16_ms, times.mean() / f16_ms, f16_diff))
-    fp16 = {"storage": "FP16 Bezier blocks, FP32 arithmetic", "ms_per_frame": f16_ms,
-            "samples_per_s": samples / (f16_ms / 1e3), "peak_rel_diff_vs_f32": f16_diff}
-    if oracle_pix is not None:
-        acc["f16"] = accuracy(out16, view, oracle_pix)
-        fp16["vs_oracle"] = acc["f16"]
-        log("FP16 blocks against the oracle: peak-relative max %.2e rms %.2e" % (acc["f16"]["max"], acc["f16"]["rms"]))
-    del vol16, sc16, out16
-    # local illumination (Sec. 4.1): the same frame with a head light
-    import dataclasses
-    sc_lit = P.Scene(vol, dataclasses.replace(P.RenderParams.of(wl), shading="headlight"))
-    for _ in range(2):
-        P.render(sc_lit, views, out=out)
-    la, lb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    la.record(stream)
-    for _ in range(args.steps):
-        P.render(sc_lit, views, out=out)
-    lb.record(stream)
-    torch.cuda.synchronize()
-    lit_ms = la.elapsed_time(lb) / args.steps
-    log("illuminated frame %.3f ms (%.2fx the plain frame)" % (lit_ms, lit_ms / times.mean()))
-    illumination = {"shading": "headlight, I = max(0.4, |l.n|)", "ms_per_frame": lit_ms,
-                    "ratio_to_plain": lit_ms / times.mean()}
+    fp16 = illumination = None
+    if args.extras:
+        # FP16 Bezier storage with FP32 arithmetic: the same frame
+        vol16 = P.Volume(wl.spline, blocks=args.blocks, dtype="f16", device=dev)
+        sc16 = P.Scene(vol16, P.RenderParams.of(wl))
+        out16 = torch.empty_like(rgba)
+        for _ in range(2):
+            P.render(sc16, views, out=out16)
+        ha, hb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ha.record(stream)
+        for _ in range(args.steps):
+            P.render(sc16, views, out=out16)
+        hb.record(stream)
+        torch.cuda.synchronize()
+        f16_ms = ha.elapsed_time(hb) / args.steps
+        f16_diff = float((out16 - rgba).abs().max() / rgba.abs().max())
+        log("FP16 blocks: %.3f ms per frame (%.2fx), peak-relative difference to FP32 %.2e" % (f16_ms, times.mean() / f16_ms, f16_diff))
+        fp16 = {"storage": "FP16 Bezier blocks, FP32 arithmetic", "ms_per_frame": f16_ms,
+                "samples_per_s": samples / (f16_ms / 1e3), "peak_rel_diff_vs_f32": f16_diff}
+        if oracle_pix is not None:
+            acc["f16"] = accuracy(out16, view, oracle_pix)
+            fp16["vs_oracle"] = acc["f16"]
+            log("FP16 blocks against the oracle: peak-relative max %.2e rms %.2e" % (acc["f16"]["max"], acc["f16"]["rms"]))
+        del vol16, sc16, out16
+        # local illumination (Sec. 4.1): the same frame with a head light
+        import dataclasses
+        sc_lit = P.Scene(vol, dataclasses.replace(P.RenderParams.of(wl), shading="headlight"))
+        for _ in range(2):
+            P.render(sc_lit, views, out=out)
+        la, lb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        la.record(stream)
+        for _ in range(args.steps):
+            P.render(sc_lit, views, out=out)
+        lb.record(stream)
+        torch.cuda.synchronize()
+        lit_ms = la.elapsed_time(lb) / args.steps
+        log("illuminated frame %.3f ms (%.2fx the plain frame)" % (lit_ms, lit_ms / times.mean()))
+        illumination = {"shading": "headlight, I = max(0.4, |l.n|)", "ms_per_frame": lit_ms,
+                        "ratio_to_plain": lit_ms / times.mean()}
     if args.copy_calib:
         n = 256 << 20
         src = torch.ones(n // 4, dtype=torch.float32, device=dev)
@@ -498,7 +509,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log("copy calibration: 3 copies of %d bytes" % n)
-    lines = stream_lines(sc, study=args.stream_study)
+    lines = stream_lines(sc, study=args.stream_study) if args.extras else None
     adjoint = adjoint_step(dev) if args.adjoint else None
     sweep = [lookup_sweep(dev, n) for n in ("vortex200k", "blobs50k")] if args.lookup_sweep else None
     serving = None
