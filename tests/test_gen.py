@@ -55,11 +55,13 @@ def test_generator_deterministic():
 
 
 def test_dyadic_knots():
+    """Minimal-span refinement at element midpoints keeps every knot dyadic
+    (a multiple of 2^-20 after 60 refinements of a 4^3 mesh), so knots are
+    exact in FP32 (R5) and the octree applies (R26)."""
     s = lrgen.small_random(p=(3, 3, 3), n=(4, 4, 4), n_ref=60, seed=3, dist="cluster")
-    for k in range(1, 16):
-        pass
     scaled = s.knots * 2.0 ** 20
     assert np.all(scaled == np.round(scaled))
+    assert np.array_equal(s.elem_box.astype(np.float32).astype(np.float64), s.elem_box)
 
 
 def test_explicit_plane_refinement():

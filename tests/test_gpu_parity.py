@@ -140,11 +140,14 @@ def test_extraction_rounding_is_rne():
 
 
 # ---------------------------------------------------------------- Eq. 4 schedule, bit for bit
-@pytest.mark.parametrize("name", ["scalar_ortho64", "scalar20k", "blobs50k", "vortex200k"])
-def test_sample_schedule_bit_exact(name):
+@pytest.mark.parametrize("name,blocks", [("scalar_ortho64", 64), ("scalar20k", 64), ("blobs50k", 64),
+                                         ("vortex200k", 64), ("vortex200k", 256), ("blobs50k", 128)])
+def test_sample_schedule_bit_exact(name, blocks):
+    """(t, element, ds) of traced rays equal the oracle's schedule, also through
+    the forests the benchmark and the serving configuration use (256^3, 128^3)."""
     import paper_1707_01170_amd as P
-    say("[gpu] trace", name)
-    wl, sc = scene(name)
+    say("[gpu] trace", name, blocks)
+    wl, sc = scene(name, blocks=blocks)
     view = wl.views[0] if name == "scalar_ortho64" else resized(wl.views[0], 96, 64)
     rng = np.random.default_rng(7)
     ii = rng.integers(0, view.width, 48)
