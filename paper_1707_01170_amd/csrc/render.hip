@@ -18,6 +18,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -222,7 +223,18 @@ struct Sample {
   TF tf;
 };
 
-template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK = LR_LOOKUP_FOREST, int SH = 0, class Visitor>
+// Deferred reloads (DF > 0).  A 16-byte wave load costs the CU's address and
+// data units about the same however few lanes it serves, and in most steps
+// of a wave some lane enters a new element, so nearly every step paid the
+// whole block's loads for a third of the lanes.  With DF > 0 a lane that
+// needs a new block waits (takes no sample this step) until at least DF
+// lanes need one, or every active lane does, or some lane has waited
+// kDeferWait steps; then they all load in the same instructions.  Each lane
+// still takes its own samples in order, so the results are unchanged.
+constexpr int kDeferWait = 3;
+
+template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK = LR_LOOKUP_FOREST, int SH = 0, int DF = 0,
+          class Visitor>
 __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, Visitor& vis) {
   constexpr int NB = (P + 1) * (P + 1) * (P + 1);
   constexpr int NCF = NCOMP * NB;
@@ -236,6 +248,7 @@ __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, V
   if (MODE == LR_STEP_FIXED) dsf = (r.t1 - r.t0) / (float)s.n_fixed;
   float t = r.t0;
   int n = 0;
+  int waited = 0;
   for (;;) {
     float ts;
     if (MODE == LR_STEP_FIXED) {
@@ -249,6 +262,16 @@ __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, V
     // Half-open containment; hi is stored as 2 where the box is closed at 1
     // (positions are clamped to [0,1]), so one comparison per bound suffices.
     const bool need = !(lo[0] <= p[0] && p[0] < hi[0] && lo[1] <= p[1] && p[1] < hi[1] && lo[2] <= p[2] && p[2] < hi[2]);
+    if constexpr (DF > 0) {
+      const uint64_t m = __ballot(need);
+      const uint64_t act = __ballot(1);
+      const bool go = __popcll(m) >= DF || m == act || __ballot(need && waited >= kDeferWait) != 0;
+      if (!go && need) {
+        ++waited;
+        continue;
+      }
+      if (need) waited = 0;
+    }
     if (need) {
       e = find_element<LK>(s, p);
       if (e < 0) {           // corrupt look-up structure: the visitor reports it
@@ -435,6 +458,19 @@ constexpr int lut_rows() {
   return (sizeof(CT) == 2 && (P == 3 || NCOMP == 3)) ? (160 * 1024 / 16) / (int)sizeof(float4) : 256;
 }
 
+// Deferral threshold of the forward kernels (see march): 32 of 64 lanes with
+// FP32 blocks (1080p vector frame 1.24 -> 1.01 ms, degree-3 blob volume
+// 0.80 -> 0.70, through the octree 1.46 -> 0.94, degree-2 scalar 0.33 ->
+// 0.32).  Off where idle lanes cost more than the loads saved: FP16 blocks
+// are half as many loads (vector frame 0.99 -> 1.16; the serving mix of
+// degree-3 scalar views saturates at 2.19e9 instead of 2.47e9 px/s, a 2048^2
+// view 1.78 -> 2.00 ms), and the illuminated kernels carry the gradient
+// contraction as well (1.66 -> 1.78).
+template <int P, int NCOMP, typename CT, int SH>
+constexpr int defer_lanes() {
+  return (SH || !std::is_same<CT, float>::value) ? 0 : 32;
+}
+
 template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK, int SH>
 __device__ __forceinline__ void render_tile(const SceneK& s, const ViewsK& vk, float4* __restrict__ rgba,
                                             uint32_t* __restrict__ nsamples, float4* lut) {
@@ -449,7 +485,7 @@ __device__ __forceinline__ void render_tile(const SceneK& s, const ViewsK& vk, f
     int n = 0;
     __device__ inline void finish(int k) { n = k; }
   } vis;
-  if (r.hit) march<P, NCOMP, CT, MODE, COLOR, LK, SH>(s, r, lut, vis);
+  if (r.hit) march<P, NCOMP, CT, MODE, COLOR, LK, SH, defer_lanes<P, NCOMP, CT, SH>()>(s, r, lut, vis);
   rgba[o] = vis.bad ? make_float4(NAN, NAN, NAN, NAN) : make_float4(vis.C[0], vis.C[1], vis.C[2], 1.0f - vis.T);
   if (nsamples) nsamples[o] = (uint32_t)vis.n;
 }
