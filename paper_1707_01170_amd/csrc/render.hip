@@ -227,10 +227,10 @@ struct Sample {
 // data units about the same however few lanes it serves, and in most steps
 // of a wave some lane enters a new element, so nearly every step paid the
 // whole block's loads for a third of the lanes.  With DF > 0 a lane that
-// needs a new block waits (takes no sample this step) until at least DF
-// lanes need one, or every active lane does, or some lane has waited
-// kDeferWait steps; then they all load in the same instructions.  Each lane
-// still takes its own samples in order, so the results are unchanged.
+// needs a new block waits (takes no sample this step) until at least 1/DF of
+// the active lanes need one, or some lane has waited kDeferWait steps; then
+// they all load in the same instructions.  Each lane still takes its own
+// samples in order, so the results are unchanged.
 constexpr int kDeferWait = 3;
 
 template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK = LR_LOOKUP_FOREST, int SH = 0, int DF = 0,
@@ -265,7 +265,7 @@ __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, V
     if constexpr (DF > 0) {
       const uint64_t m = __ballot(need);
       const uint64_t act = __ballot(1);
-      const bool go = __popcll(m) >= DF || m == act || __ballot(need && waited >= kDeferWait) != 0;
+      const bool go = __popcll(m) * DF >= __popcll(act) || __ballot(need && waited >= kDeferWait) != 0;
       if (!go && need) {
         ++waited;
         continue;
@@ -458,17 +458,19 @@ constexpr int lut_rows() {
   return (sizeof(CT) == 2 && (P == 3 || NCOMP == 3)) ? (160 * 1024 / 16) / (int)sizeof(float4) : 256;
 }
 
-// Deferral threshold of the forward kernels (see march): 32 of 64 lanes with
-// FP32 blocks (1080p vector frame 1.24 -> 1.01 ms, degree-3 blob volume
-// 0.80 -> 0.70, through the octree 1.46 -> 0.94, degree-2 scalar 0.33 ->
-// 0.32).  Off where idle lanes cost more than the loads saved: FP16 blocks
+// Deferral of the forward kernels (see march): reload once half the active
+// lanes need a block, with FP32 blocks (1080p vector frame 1.24 -> 0.99 ms,
+// degree-3 blob volume 0.80 -> 0.71, through the octree 1.46 -> 0.92,
+// degree-2 scalar 0.33 -> 0.31; fixed counts of 8 to 48 lanes and waits of 2
+// to 8 steps were no better).  Off where idle lanes cost more than the loads
+// saved: FP16 blocks
 // are half as many loads (vector frame 0.99 -> 1.16; the serving mix of
 // degree-3 scalar views saturates at 2.19e9 instead of 2.47e9 px/s, a 2048^2
 // view 1.78 -> 2.00 ms), and the illuminated kernels carry the gradient
 // contraction as well (1.66 -> 1.78).
 template <int P, int NCOMP, typename CT, int SH>
 constexpr int defer_lanes() {
-  return (SH || !std::is_same<CT, float>::value) ? 0 : 32;
+  return (SH || !std::is_same<CT, float>::value) ? 0 : 2;
 }
 
 template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK, int SH>
