@@ -469,7 +469,7 @@ constexpr int lut_rows() {
 // view 1.78 -> 2.00 ms), and the illuminated kernels carry the gradient
 // contraction as well (1.66 -> 1.78).
 template <int P, int NCOMP, typename CT, int SH>
-constexpr int defer_lanes() {
+constexpr int defer_divisor() {
   return (SH || !std::is_same<CT, float>::value) ? 0 : 2;
 }
 
@@ -487,7 +487,7 @@ __device__ __forceinline__ void render_tile(const SceneK& s, const ViewsK& vk, f
     int n = 0;
     __device__ inline void finish(int k) { n = k; }
   } vis;
-  if (r.hit) march<P, NCOMP, CT, MODE, COLOR, LK, SH, defer_lanes<P, NCOMP, CT, SH>()>(s, r, lut, vis);
+  if (r.hit) march<P, NCOMP, CT, MODE, COLOR, LK, SH, defer_divisor<P, NCOMP, CT, SH>()>(s, r, lut, vis);
   rgba[o] = vis.bad ? make_float4(NAN, NAN, NAN, NAN) : make_float4(vis.C[0], vis.C[1], vis.C[2], 1.0f - vis.T);
   if (nsamples) nsamples[o] = (uint32_t)vis.n;
 }
