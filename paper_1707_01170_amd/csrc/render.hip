@@ -588,6 +588,15 @@ __global__ void lookup_octree_kernel(const uint32_t* __restrict__ root, const ui
 // read would wait behind the wave's queued atomics.  On gfx950 an LDS FP64
 // atomic add to distinct addresses issues ~20x faster than an FP32 one
 // (measured ~11 against ~195 CU cycles per wavefront instruction).
+//
+// The re-march gathers reloads as the forward kernels do (march, DF = 2), so
+// the lanes that leave their elements in one step also deposit their sums in
+// one set of table atomics (backward 1.85 -> 1.70 ms on the 4 x 512^2 scalar
+// step; a third or a quarter of the lanes, or all of them: 1.74 / 1.76 /
+// 1.72).  A waiting lane is inactive in any spill meanwhile; a spill count in
+// LDS tells it, when it deposits, that its entry claim must be made again.
+constexpr int kAdjointDefer = 2;
+
 template <int P>
 struct GradTable {
   static constexpr int NB = (P + 1) * (P + 1) * (P + 1);
@@ -598,10 +607,11 @@ struct GradTable {
 };
 
 // The active lanes write every non-zero entry of the element table to the
-// global gradient (FP32 atomics) and clear the table.  The wave's LDS
+// global gradient (FP32 atomics), clear the table and count the spill.  The wave's LDS
 // operations complete in order, so every tag is read before it is cleared.
 template <int NB, int S>
-__device__ inline void spill_table(float* __restrict__ gbez, int64_t stride, int32_t* htag, double* hval) {
+__device__ inline void spill_table(float* __restrict__ gbez, int64_t stride, int32_t* htag, double* hval,
+                                   int32_t* epoch) {
   const uint64_t act = __ballot(1);
   const int na = __popcll(act);
   const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
@@ -612,6 +622,9 @@ __device__ inline void spill_table(float* __restrict__ gbez, int64_t stride, int
     hval[i] = 0.0;
   }
   for (int i = rank; i < S; i += na) htag[i] = -1;
+  // atomic accesses: with plain ones the compiler may keep the count in a
+  // register across the march loop, and lanes would disagree on it
+  if (rank == 0) __hip_atomic_fetch_add(epoch, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 template <int P>
@@ -627,6 +640,8 @@ struct Adjoint : Composite {
   double* glut_s;             // LDS [256][4]
   int32_t* htag;              // LDS [kSlots]: element id or -1
   double* hval;               // LDS [kSlots][NB]
+  int32_t* epoch;             // LDS: spills of the table so far
+  int32_t seen = 0;           // the spill count when the lane last claimed
   float range_scale;          // 255 / (vmax - vmin)
   const float4* lut;
   int32_t cur = -1;
@@ -663,24 +678,31 @@ struct Adjoint : Composite {
   // Adds the sums of the element the lane leaves (cur) into the table.  Every
   // active lane calls it (with cur < 0 if it has nothing to add), so that a
   // full table can be spilled by the whole wave.
-  __device__ inline void deposit(bool want) {
+  __device__ inline int32_t deposit(bool want) {
+    // A lane that waited for a gathered reload step (or whose ray ended) was
+    // inactive in any spill meanwhile, so its entry claim may be stale.
+    int32_t ep = __hip_atomic_load(epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (want && ep != seen) claim = atomicCAS(&htag[h_cur], -1, cur);
     int32_t ref = want ? resolve() : 0;
     if (__ballot(want && ref < 0)) {
-      spill_table<NB, kSlots * GradTable<P>::kCopies>(gbez, stride, htag, hval);
+      spill_table<NB, kSlots * GradTable<P>::kCopies>(gbez, stride, htag, hval, epoch);
+      ++ep;
       if (cur >= 0) claim = atomicCAS(&htag[h_cur], -1, cur);
+      seen = ep;
       if (want) ref = resolve();
     }
-    if (!want) return;
+    if (!want) return ep;
     if (ref >= 0) {
       double* v = hval + ref * NB;
 #pragma unroll
       for (int j = 0; j < NB; ++j) atomicAdd(v + j, (double)acc[j]);   // straight-line, no per-value branches
-      return;
+      return ep;
     }
     float* out = gbez + (int64_t)cur * stride;             // still no slot: straight to global memory
 #pragma unroll
     for (int j = 0; j < NB; ++j)
       if (acc[j] != 0.0f) unsafeAtomicAdd(out + j, acc[j]);
+    return ep;
   }
 
   __device__ inline bool sample(const SceneK& s, const Sample<P>& sm) {
@@ -719,9 +741,10 @@ struct Adjoint : Composite {
     g_s = fmaf(g_x[3], l1.w - l0.w, g_s);
     const float g_v = sm.tf.inside ? g_s * range_scale : 0.0f;
     const bool enter = sm.e != cur;
-    deposit(enter && cur >= 0);
+    const int32_t ep = deposit(enter && cur >= 0);
     if (enter) {
       cur = sm.e;
+      seen = ep;
       // Claim the element's slot now; the result is first needed when the
       // lane leaves the element, so the compare-and-swap's latency is hidden
       // behind the element's samples.
@@ -748,8 +771,7 @@ struct Adjoint : Composite {
   }
   __device__ inline void finish(int) {
     // A lane whose ray ended early waited here while the others marched on;
-    // if they spilled the table meanwhile, its entry claim is stale: claim again.
-    if (cur >= 0) claim = atomicCAS(&htag[h_cur], -1, cur);
+    // deposit claims again if they spilled the table meanwhile.
     deposit(cur >= 0);
     flush_row();
   }
@@ -763,6 +785,8 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(const SceneK s, cons
   __shared__ double glut_s[1024];
   __shared__ int32_t htag[S];
   __shared__ double hval[S * NB];
+  __shared__ int32_t epoch;
+  if (threadIdx.x == 0) epoch = 0;
   for (int i = threadIdx.x; i < 1024; i += kThreads) glut_s[i] = 0.0;
   for (int i = threadIdx.x; i < S; i += kThreads) htag[i] = -1;
   for (int i = threadIdx.x; i < S * NB; i += kThreads) hval[i] = 0.0;
@@ -789,9 +813,10 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(const SceneK s, cons
       vis.glut_s = glut_s;
       vis.htag = htag;
       vis.hval = hval;
+      vis.epoch = &epoch;
       vis.range_scale = 255.0f * s.inv_range;
       vis.lut = s.lut;
-      march<P, 1, float, MODE, LR_COLOR_LUT, LK>(s, r, s.lut, vis);
+      march<P, 1, float, MODE, LR_COLOR_LUT, LK, 0, kAdjointDefer>(s, r, s.lut, vis);
     }
   }
   __syncthreads();
