@@ -109,7 +109,10 @@ def test_fp16_blocks_equal_fp32_kernel_on_widened_blocks(name, shading):
     """FP16 blocks are widened exactly (inside each multiply-add, or when the
     block is loaded in the illuminated vector kernel), so a render from FP16
     blocks equals, bit for bit, the FP32 kernels' render of the same values
-    stored as FP32."""
+    stored as FP32.  The plain FP32 kernels gather block reloads (a lane
+    waits until half of its wave's active lanes need one) while the FP16
+    ones reload at once, so this also pins that the gathering leaves every
+    sample unchanged."""
     import paper_1707_01170_amd as P
     say("[gpu] fp16 == fp32 on widened blocks", name, shading)
     wl, sc16 = scene(name, blocks=64, dtype="f16")
@@ -122,6 +125,26 @@ def test_fp16_blocks_equal_fp32_kernel_on_widened_blocks(name, shading):
     b, _, _ = P.render(P.Scene(sc32.volume, prm), [view], bezier=widened)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("name,blocks", [("vortex200k", 256), ("blobs50k", 128)])
+def test_gathered_reloads_leave_the_full_frame_unchanged(name, blocks):
+    """The benchmark's frame (vortex200k at 1920x1080 through the 256^3
+    forest) and the serving volume's view, rendered by the FP32 kernel, which
+    gathers block reloads, and by the FP16 kernel, which reloads at once, from
+    the same block values: identical bit for bit."""
+    import paper_1707_01170_amd as P
+    say("[gpu] gathered reloads, full frame", name, blocks)
+    wl, sc16 = scene(name, blocks=blocks, dtype="f16")
+    _, sc32 = scene(name, blocks=blocks)
+    view = wl.views[0]
+    prm = P.RenderParams.of(wl)
+    a, _, na = P.render(P.Scene(sc16.volume, prm), [view], nsamples=True)
+    widened = sc16.volume.bezier.float()[:, :sc32.volume.bezier.shape[1]].contiguous()
+    b, _, nb = P.render(P.Scene(sc32.volume, prm), [view], bezier=widened, nsamples=True)
+    torch.cuda.synchronize()
+    say("%s %dx%d: %d samples" % (name, view.width, view.height, int(nb.sum())))
+    assert torch.equal(na, nb) and torch.equal(a, b)
 
 
 @pytest.mark.parametrize("name", ["blobs50k", "scalar20k"])
