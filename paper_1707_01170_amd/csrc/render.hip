@@ -268,6 +268,7 @@ __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, V
       const bool go = __popcll(m) * DF >= __popcll(act) || __ballot(need && waited >= kDeferWait) != 0;
       if (!go && need) {
         ++waited;
+        vis.wait();
         continue;
       }
       if (need) waited = 0;
@@ -376,6 +377,7 @@ struct Composite {
   float T = 1.0f;
   bool bad = false;          // the look-up met a corrupt reference
   __device__ inline void corrupt(float) { bad = true; }
+  __device__ inline void wait() {}
   __device__ inline float opacity(const SceneK& s, float alpha, float ds) const {
     return opacity_of(alpha, ds * s.inv_xi);
   }
@@ -593,8 +595,12 @@ __global__ void lookup_octree_kernel(const uint32_t* __restrict__ root, const ui
 // the lanes that leave their elements in one step also deposit their sums in
 // one set of table atomics (backward 1.85 -> 1.70 ms on the 4 x 512^2 scalar
 // step; a third or a quarter of the lanes, or all of them: 1.74 / 1.76 /
-// 1.72).  A waiting lane is inactive in any spill meanwhile; a spill count in
-// LDS tells it, when it deposits, that its entry claim must be made again.
+// 1.72).  A waiting lane is inactive in any spill meanwhile, so it claims
+// its slot again when it deposits (march tells the visitor when a lane
+// waits).  A count of spills in LDS, read every step, did the same job but
+// cost a wait for the step's queued LDS atomics (1.60 against 1.59 ms);
+// spilling at the top of the next step, where every marching lane is
+// active, sent the failing lanes' sums to global atomics (2.06 ms).
 constexpr int kAdjointDefer = 2;
 
 template <int P>
@@ -610,8 +616,7 @@ struct GradTable {
 // global gradient (FP32 atomics), clear the table and count the spill.  The wave's LDS
 // operations complete in order, so every tag is read before it is cleared.
 template <int NB, int S>
-__device__ inline void spill_table(float* __restrict__ gbez, int64_t stride, int32_t* htag, double* hval,
-                                   int32_t* epoch) {
+__device__ inline void spill_table(float* __restrict__ gbez, int64_t stride, int32_t* htag, double* hval) {
   const uint64_t act = __ballot(1);
   const int na = __popcll(act);
   const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
@@ -622,9 +627,6 @@ __device__ inline void spill_table(float* __restrict__ gbez, int64_t stride, int
     hval[i] = 0.0;
   }
   for (int i = rank; i < S; i += na) htag[i] = -1;
-  // atomic accesses: with plain ones the compiler may keep the count in a
-  // register across the march loop, and lanes would disagree on it
-  if (rank == 0) __hip_atomic_fetch_add(epoch, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 template <int P>
@@ -640,8 +642,7 @@ struct Adjoint : Composite {
   double* glut_s;             // LDS [256][4]
   int32_t* htag;              // LDS [kSlots]: element id or -1
   double* hval;               // LDS [kSlots][NB]
-  int32_t* epoch;             // LDS: spills of the table so far
-  int32_t seen = 0;           // the spill count when the lane last claimed
+  bool waited = false;        // the lane skipped a step since its last claim
   float range_scale;          // 255 / (vmax - vmin)
   const float4* lut;
   int32_t cur = -1;
@@ -678,32 +679,32 @@ struct Adjoint : Composite {
   // Adds the sums of the element the lane leaves (cur) into the table.  Every
   // active lane calls it (with cur < 0 if it has nothing to add), so that a
   // full table can be spilled by the whole wave.
-  __device__ inline int32_t deposit(bool want) {
-    // A lane that waited for a gathered reload step (or whose ray ended) was
-    // inactive in any spill meanwhile, so its entry claim may be stale.
-    int32_t ep = __hip_atomic_load(epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (want && ep != seen) claim = atomicCAS(&htag[h_cur], -1, cur);
+  // Adds the sums of the element the lane leaves (cur) into the table.  Every
+  // active lane calls it (with cur < 0 if it has nothing to add), so that a
+  // full table can be spilled by the whole wave.  A lane that waited for a
+  // gathered reload step was inactive in any spill meanwhile, so its entry
+  // claim may be stale: it claims again.
+  __device__ inline void deposit(bool want) {
+    if (want && waited) claim = atomicCAS(&htag[h_cur], -1, cur);
     int32_t ref = want ? resolve() : 0;
     if (__ballot(want && ref < 0)) {
-      spill_table<NB, kSlots * GradTable<P>::kCopies>(gbez, stride, htag, hval, epoch);
-      ++ep;
+      spill_table<NB, kSlots * GradTable<P>::kCopies>(gbez, stride, htag, hval);
       if (cur >= 0) claim = atomicCAS(&htag[h_cur], -1, cur);
-      seen = ep;
       if (want) ref = resolve();
     }
-    if (!want) return ep;
+    if (!want) return;
     if (ref >= 0) {
       double* v = hval + ref * NB;
 #pragma unroll
       for (int j = 0; j < NB; ++j) atomicAdd(v + j, (double)acc[j]);   // straight-line, no per-value branches
-      return ep;
+      return;
     }
     float* out = gbez + (int64_t)cur * stride;             // still no slot: straight to global memory
 #pragma unroll
     for (int j = 0; j < NB; ++j)
       if (acc[j] != 0.0f) unsafeAtomicAdd(out + j, acc[j]);
-    return ep;
   }
+  __device__ inline void wait() { waited = true; }
 
   __device__ inline bool sample(const SceneK& s, const Sample<P>& sm) {
     const float a = opacity(s, sm.alpha, sm.ds);
@@ -715,14 +716,18 @@ struct Adjoint : Composite {
     // g_a only reaches the table through da/dalpha, which has the factor om.
     const float om = 1.0f - a;
     const bool live = om > 0.0f;
-    float g_a = live ? gA * Tfin / om : gA * T;
+    // hardware reciprocals (~1 ulp) in place of correctly rounded divisions
+    // (five of those cost ~60 instructions per sample; 1.72 -> 1.62 ms):
+    // these values feed only the gradient, never the march
+    const float inv_om = live ? __builtin_amdgcn_rcpf(om) : 0.0f;
+    float g_a = live ? gA * Tfin * inv_om : gA * T;
     float g_x[4];
     for (int ch = 0; ch < 3; ++ch) {
       g_x[ch] = gC[ch] * w;
-      g_a = fmaf(gC[ch], T * sm.csrc[ch] - (live ? (Cfin[ch] - Cn[ch]) / om : 0.0f), g_a);
+      g_a = fmaf(gC[ch], T * sm.csrc[ch] - (Cfin[ch] - Cn[ch]) * inv_om, g_a);
     }
     const float r = sm.ds * s.inv_xi;
-    g_x[3] = sm.clamped ? 0.0f : g_a * r * om / (1.0f - sm.alpha);
+    g_x[3] = sm.clamped ? 0.0f : g_a * r * om * __builtin_amdgcn_rcpf(1.0f - sm.alpha);
     // table rows
     if (sm.tf.i0 != row) {
       flush_row();
@@ -741,10 +746,10 @@ struct Adjoint : Composite {
     g_s = fmaf(g_x[3], l1.w - l0.w, g_s);
     const float g_v = sm.tf.inside ? g_s * range_scale : 0.0f;
     const bool enter = sm.e != cur;
-    const int32_t ep = deposit(enter && cur >= 0);
+    deposit(enter && cur >= 0);
     if (enter) {
       cur = sm.e;
-      seen = ep;
+      waited = false;
       // Claim the element's slot now; the result is first needed when the
       // lane leaves the element, so the compare-and-swap's latency is hidden
       // behind the element's samples.
@@ -771,7 +776,9 @@ struct Adjoint : Composite {
   }
   __device__ inline void finish(int) {
     // A lane whose ray ended early waited here while the others marched on;
-    // deposit claims again if they spilled the table meanwhile.
+    // if they spilled the table meanwhile, its claim is stale: claim again.
+    if (cur >= 0) claim = atomicCAS(&htag[h_cur], -1, cur);
+    waited = false;
     deposit(cur >= 0);
     flush_row();
   }
@@ -785,8 +792,6 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(const SceneK s, cons
   __shared__ double glut_s[1024];
   __shared__ int32_t htag[S];
   __shared__ double hval[S * NB];
-  __shared__ int32_t epoch;
-  if (threadIdx.x == 0) epoch = 0;
   for (int i = threadIdx.x; i < 1024; i += kThreads) glut_s[i] = 0.0;
   for (int i = threadIdx.x; i < S; i += kThreads) htag[i] = -1;
   for (int i = threadIdx.x; i < S * NB; i += kThreads) hval[i] = 0.0;
@@ -813,7 +818,6 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(const SceneK s, cons
       vis.glut_s = glut_s;
       vis.htag = htag;
       vis.hval = hval;
-      vis.epoch = &epoch;
       vis.range_scale = 255.0f * s.inv_range;
       vis.lut = s.lut;
       march<P, 1, float, MODE, LR_COLOR_LUT, LK, 0, kAdjointDefer>(s, r, s.lut, vis);
