@@ -55,72 +55,81 @@ __device__ inline double dunkey(unsigned long long k) {
   return x;
 }
 
-// Bernstein coefficients beta[0..p] of the B-spline with local knots
-// u[0..p+1] on [a, b], which must lie inside the non-empty knot span
-// [u_S, u_S+1].  Padded knot vector T[R] = u[clamp(R - p, 0, p + 1)]; the
-// B-spline is basis function p of T and the span is span k = S + p of T.
-// Degree and span are template parameters, so the recurrence is unrolled,
-// the knots stay in registers and divisions repeated across j are computed
-// once (the arithmetic of every value is unchanged).
-template <int P, int S>
-__device__ inline void bezier_span(const double (&u)[P + 2], double a, double b, double* beta) {
-  constexpr int k = S + P;
-  auto T = [&](int R) {
-    int i = R - P;
-    i = i < 0 ? 0 : (i > P + 1 ? P + 1 : i);
-    return u[i];
-  };
+// Bernstein coefficients beta[0..P] of the B-spline with local knots
+// u[0..P+1] on [a, b], which must lie inside one non-empty knot span [u_S,
+// u_S+1] (the first such span is taken; false if there is none).  With the
+// knot vector padded by repeating its end knots, T[R] = u[clamp(R - P, 0,
+// P + 1)], the B-spline is basis function P of T and the span is span S + P
+// of T; beta_j = blossom(a^(P-j), b^j) by de Boor's recurrence, one knot
+// argument per level.  The knots the recurrence reads, T[S + q] for
+// q = 1..2P, are gathered once into a window by selects, so the lanes of a
+// wavefront run the same code whatever their span: the B-splines acting on
+// one element sit in all P+1 spans along each axis, and code unrolled per
+// span ran the P+1 variants one after another (vortex200k 0.72 -> 0.57 ms,
+// blobs50k 0.54 -> 0.34, the same values bit for bit).  Divisions repeated
+// across j are computed once.
+template <int P>
+__device__ inline bool bezier_span(const double (&u)[P + 2], double a, double b, double (&beta)[P + 1]) {
+  int S = -1;
+#pragma unroll
+  for (int s = P; s >= 0; --s)
+    if (u[s] < u[s + 1] && u[s] <= a && b <= u[s + 1]) S = s;
+  if (S < 0) return false;
+  double W[2 * P + 1];   // W[q] = T[S + q]
+#pragma unroll
+  for (int q = 1; q <= 2 * P; ++q) {
+    double w = u[0];
+#pragma unroll
+    for (int i = 1; i <= P + 1; ++i) w = S + q - P >= i ? u[i] : w;
+    W[q] = w;
+  }
 #pragma unroll
   for (int j = 0; j <= P; ++j) {
     double d[P + 1];
 #pragma unroll
-    for (int r = 0; r <= P; ++r) d[r] = (k - P + r == P) ? 1.0 : 0.0;
+    for (int r = 0; r <= P; ++r) d[r] = r == P - S ? 1.0 : 0.0;
 #pragma unroll
     for (int l = 1; l <= P; ++l) {
       const double x = (l <= P - j) ? a : b;
 #pragma unroll
       for (int r = P; r >= l; --r) {
-        const int R = k - P + r;
-        const double tr = T(R);
-        const double al = (x - tr) / (T(R + P + 1 - l) - tr);
+        const double tr = W[r];
+        const double al = (x - tr) / (W[r + P + 1 - l] - tr);
         d[r] = (1.0 - al) * d[r - 1] + al * d[r];
       }
     }
     beta[j] = d[P];
   }
+  return true;
 }
 
-// The first span S of u that is non-empty and contains [a, b].
-template <int P, int S = 0>
-__device__ inline bool bezier_spans(const double (&u)[P + 2], double a, double b, double* beta) {
-  if constexpr (S > P) {
-    return false;
-  } else {
-    if (u[S] < u[S + 1] && u[S] <= a && b <= u[S + 1]) {
-      bezier_span<P, S>(u, a, b, beta);
-      return true;
-    }
-    return bezier_spans<P, S + 1>(u, a, b, beta);
-  }
-}
-
+// The B-spline's Bernstein vector on [a, b] written to out[0..3] (zeros
+// beyond P and on failure).  Each degree writes its own vector to the
+// caller's (LDS) row: returning it through one local array for all degrees
+// made the compiler index that array at run time, in scratch memory.
 template <int P>
-__device__ inline bool bezier_1d_p(const double* ug, double a, double b, double* beta) {
+__device__ inline bool bezier_1d_p(const double* ug, double a, double b, double* out) {
   double u[P + 2];
 #pragma unroll
   for (int i = 0; i < P + 2; ++i) u[i] = ug[i];
-  return bezier_spans<P>(u, a, b, beta);
+  double beta[P + 1];
+  const bool ok = bezier_span<P>(u, a, b, beta);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) out[j] = (ok && j <= P) ? beta[j] : 0.0;
+  return ok;
 }
 
-// Bernstein coefficients beta[0..p] of the B-spline with local knots
-// u[0..p+1] (global memory) on [a, b]; false if [a, b] is not inside one
+// Bernstein coefficients of the B-spline with local knots u[0..p+1] (global
+// memory) on [a, b], into out[0..3]; false if [a, b] is not inside one
 // non-empty knot span.
-__device__ inline bool bezier_1d(const double* u, int p, double a, double b, double* beta) {
+__device__ inline bool bezier_1d(const double* u, int p, double a, double b, double* out) {
   switch (p) {
-    case 1: return bezier_1d_p<1>(u, a, b, beta);
-    case 2: return bezier_1d_p<2>(u, a, b, beta);
-    case 3: return bezier_1d_p<3>(u, a, b, beta);
-    default: return false;
+    case 1: return bezier_1d_p<1>(u, a, b, out);
+    case 2: return bezier_1d_p<2>(u, a, b, out);
+    case 3: return bezier_1d_p<3>(u, a, b, out);
+    default:
+      for (int j = 0; j < 4; ++j) out[j] = 0.0;
+      return false;
   }
 }
 
@@ -158,7 +167,11 @@ __global__ void range_final(unsigned long long* r) {
 // elements and merged into the global pair once per wavefront, and only if it
 // extends the pair as last seen: one global atomic per element on the same
 // two words serialised the whole launch.
-__global__ __launch_bounds__(kLanes) void extract_kernel(ExtractArgs a) {
+//
+// Compiled for four waves per SIMD (127 registers; left alone the compiler
+// takes 129 and three waves fit): vortex200k 0.63 -> 0.51 ms, blobs50k 0.34
+// -> 0.31.
+__global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(4))) void extract_kernel(ExtractArgs a) {
   __shared__ double sb[kLanes][3][4];
   __shared__ double sw[kLanes][4];
   __shared__ double so[256];
@@ -176,9 +189,8 @@ __global__ __launch_bounds__(kLanes) void extract_kernel(ExtractArgs a) {
         const int32_t bi = a.csr_idx[q];
         bool ok = bi >= 0 && bi < a.n_bspl;
         for (int d = 0; d < 3; ++d) {
-          double beta[4] = {0.0, 0.0, 0.0, 0.0};
-          if (ok) ok = bezier_1d(a.knots + ((int64_t)bi * 3 + d) * a.kstride, a.p[d], eb[d], eb[3 + d], beta);
-          for (int j = 0; j < 4; ++j) sb[lane][d][j] = beta[j];
+          if (ok) ok = bezier_1d(a.knots + ((int64_t)bi * 3 + d) * a.kstride, a.p[d], eb[d], eb[3 + d], sb[lane][d]);
+          else for (int j = 0; j < 4; ++j) sb[lane][d][j] = 0.0;
         }
         for (int c = 0; c < 4; ++c)
           sw[lane][c] = (ok && c < a.ncomp) ? a.gamma[bi] * a.coef[(int64_t)bi * a.ncomp + c] : 0.0;
@@ -245,9 +257,13 @@ __global__ __launch_bounds__(kLanes) void extract_kernel(ExtractArgs a) {
 // split and the same 1-D Bernstein vectors; each lane contracts the element's
 // gradient block with its B-spline's tensor Bernstein coefficients and adds
 // gamma_i times the result to dL/dc_i.  Elements whose gradient block is zero
-// (no ray reached them) add nothing.
+// (no ray reached them) add nothing.  Each lane's Bernstein vectors live in an
+// LDS row: the contraction reads them at run-time indices, which a register
+// array would serve from scratch memory (vortex200k 1.27 -> 0.82 ms, blobs50k
+// 0.63 -> 0.37).
 __global__ __launch_bounds__(kLanes) void extract_backward_kernel(ExtractArgs a) {
   __shared__ double sg[256];
+  __shared__ double sbeta[kLanes][3][4];   // each lane's Bernstein vectors (read at run-time indices)
   const int64_t e = blockIdx.x;
   const int lane = threadIdx.x;
   const int NC = a.nb * a.ncomp;
@@ -266,7 +282,7 @@ __global__ __launch_bounds__(kLanes) void extract_backward_kernel(ExtractArgs a)
   for (int64_t q = b0 + lane; q < b1; q += kLanes) {
     const int32_t bi = a.csr_idx[q];
     if (bi < 0 || bi >= a.n_bspl) continue;
-    double beta[3][4];
+    double (&beta)[3][4] = sbeta[lane];
     bool ok = true;
     for (int d = 0; d < 3 && ok; ++d)
       ok = bezier_1d(a.knots + ((int64_t)bi * 3 + d) * a.kstride, a.p[d], eb[d], eb[3 + d], beta[d]);
