@@ -230,7 +230,9 @@ struct Sample {
 // needs a new block waits (takes no sample this step) until at least 1/DF of
 // the active lanes need one, or some lane has waited kDeferWait steps; then
 // they all load in the same instructions.  Each lane still takes its own
-// samples in order, so the results are unchanged.
+// samples in order, so the results are unchanged.  The visitor hears of each
+// step a lane skips (vis.wait()): the adjoint's lanes are inactive in any
+// table spill meanwhile.
 constexpr int kDeferWait = 3;
 
 template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK = LR_LOOKUP_FOREST, int SH = 0, int DF = 0,
