@@ -32,7 +32,7 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ("render.hip", "eval.h", "common.h")
+KERNEL_SOURCES = ("render.hip", "eval.h", "common.h", "lookup.h", "schedule.h")
 
 
 def kernel_digest() -> str:

@@ -23,6 +23,7 @@
 
 #include "common.h"
 #include "eval.h"
+#include "schedule.h"
 
 namespace {
 
@@ -426,14 +427,20 @@ struct TraceVisitor : Composite {
 
 // Work distribution.  The hardware deals consecutive workgroups to the
 // eight XCDs in turn: workgroup b runs on XCD b mod 8.  The tiles are grouped
-// in blocks of kQuad x kQuad (row-major over each view); XCD x renders the
-// blocks x, x + 8, x + 16, ..., one workgroup per tile, so a block's rays,
-// which share elements, meet in one XCD's L2, while every XCD gets blocks
-// from all over the image.  The work per pixel is very uneven (rays through
-// dense regions take several times more samples): giving each XCD one
-// contiguous band of the image instead left the busiest XCD with ~1.9x the
-// mean work.  b -> (block, tile) is a bijection onto the blocks padded to a
-// multiple of 8; tiles outside the image do nothing.
+// in blocks of kQuad x kQuad; XCD x renders the blocks x, x + 8, x + 16, ...
+// of a view, one workgroup per tile, so a block's rays, which share
+// elements, meet in one XCD's L2, while every XCD gets blocks from all over
+// the image.  The work per pixel is very uneven (rays through dense regions
+// take several times more samples): giving each XCD one contiguous band of
+// the image instead left the busiest XCD with ~1.9x the mean work.  Blocks
+// are dealt from the middle of the view outwards (ring_cell), because the
+// rays through the middle of the volume are the long ones: dispatched first,
+// they no longer finish alone at the end of the launch (1080p vector frame
+// 1.00 -> 0.88 ms, degree-3 blob view 0.71 -> 0.61, illuminated 1.66 ->
+// 1.51, images unchanged; dealt row by row, a one-view launch took 20 %
+// longer per view than a launch of four copies of it).  b -> (block, tile)
+// is a bijection onto the blocks padded to a multiple of 8; tiles outside
+// the image do nothing.
 __device__ inline bool locate(const ViewsK& vk, int64_t b, int& v, int& px, int& py) {
   constexpr int QQ = kQuad * kQuad;
   const int64_t k = b >> 3;
@@ -443,8 +450,11 @@ __device__ inline bool locate(const ViewsK& vk, int64_t b, int& v, int& px, int&
   if (q >= vk.quad_base[vk.n]) return false;
   while (v + 1 < vk.n && q >= vk.quad_base[v + 1]) ++v;
   const int64_t lq = q - vk.quad_base[v];
-  const int gx = (int)(lq % vk.quads_x[v]) * kQuad + w % kQuad;
-  const int gy = (int)(lq / vk.quads_x[v]) * kQuad + w / kQuad;
+  const int qw = vk.quads_x[v], qh = (int)((vk.quad_base[v + 1] - vk.quad_base[v]) / qw);
+  int qx, qy;
+  ring_cell(lq, qw, qh, qx, qy);
+  const int gx = qx * kQuad + w % kQuad;
+  const int gy = qy * kQuad + w / kQuad;
   const int lane = threadIdx.x & 63;
   px = gx * kGroup + (lane & 7);
   py = gy * kGroup + (lane >> 3);

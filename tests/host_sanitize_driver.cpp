@@ -12,6 +12,7 @@
 
 #include "lrvr.h"
 #include "../paper_1707_01170_amd/csrc/lookup.h"
+#include "../paper_1707_01170_amd/csrc/schedule.h"
 
 namespace {
 
@@ -150,10 +151,33 @@ void check_kernel_octree(uint32_t root, std::vector<uint32_t> nodes, const std::
   check(n_bad > 0 && n_loop > 0, "octree: corrupt references are reported, not followed");
 }
 
+// The render launch's dispatch order (ring_cell) visits every cell of a
+// grid exactly once, first the middle one.
+void check_ring_order() {
+  bool ok = true;
+  std::vector<int> seen;
+  auto grid = [&](int w, int h) {
+    seen.assign((size_t)w * h, 0);
+    for (int64_t k = 0; k < (int64_t)w * h && ok; ++k) {
+      int x = -1, y = -1;
+      lrvr::ring_cell(k, w, h, x, y);
+      ok = x >= 0 && x < w && y >= 0 && y < h && seen[(size_t)y * w + x]++ == 0;
+      if (k == 0) ok = ok && x == (w - 1) / 2 && y == (h - 1) / 2;
+    }
+  };
+  for (int w = 1; w <= 48 && ok; ++w)
+    for (int h = 1; h <= 48 && ok; ++h) grid(w, h);
+  const int shapes[][2] = {{120, 68}, {68, 120}, {256, 256}, {1024, 3}, {3, 1024}};
+  for (const auto& s : shapes)
+    if (ok) grid(s[0], s[1]);
+  check(ok, "ring order: a bijection onto the grid, starting in the middle");
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
   if (argc != 2) return 2;
+  check_ring_order();
   FILE* f = std::fopen(argv[1], "rb");
   if (!f) return 2;
   int32_t p[3], kstride, dyadic;
