@@ -306,6 +306,28 @@ typedef struct {
 lr_status lr_render(const lr_scene* sc, const lr_view* views, int32_t n_views, float* rgba,
                     uint32_t* nsamples, void* stream);
 
+/* lr_render with a dispatch order estimated per launch: the same images, bit
+ * for bit, and the same errors, in less time when the work per pixel is
+ * uneven.  A launch's blocks of 16x16 pixels are dealt to the GPU longest
+ * first; a block's cost is estimated from the element sizes (Eq. 4 steps) at
+ * 64 points along its centre ray, and lr_render instead deals the blocks from
+ * the middle of each view outwards.
+ * workspace        device memory, 256-byte aligned, of at least the bytes
+ *                  lr_render_workspace_size returns for the same views; the
+ *                  caller owns it; it is read and written on stream only, so
+ *                  it may be reused once this call's work on stream is done
+ * workspace_bytes  its size: LR_ECAPACITY if too small, LR_EINVAL if null or
+ *                  misaligned */
+lr_status lr_render_scheduled(const lr_scene* sc, const lr_view* views, int32_t n_views, float* rgba,
+                              uint32_t* nsamples, void* workspace, int64_t workspace_bytes,
+                              void* stream);
+
+/* Bytes of workspace lr_render_scheduled needs for these views (host only,
+ * no GPU work): 8 bytes per 16x16-pixel block of the largest launch (16
+ * views per launch), each half rounded up to 256.  LR_EINVAL for null
+ * arguments or invalid views. */
+lr_status lr_render_workspace_size(const lr_view* views, int32_t n_views, int64_t* bytes);
+
 /* Adjoint of lr_render for scalar fields (ncomp 1, LR_COLOR_LUT, F32 blocks,
  * either look-up structure, no shading).
  * Re-marches each ray with the forward's schedule (no per-sample storage) and

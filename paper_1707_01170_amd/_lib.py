@@ -83,6 +83,9 @@ SIGNATURES = {
     "lr_extract_bezier": (_c_i32, [ctypes.POINTER(LRSplineDev), _c_i32, _vp, _vp, _vp]),
     "lr_extract_bezier_backward": (_c_i32, [ctypes.POINTER(LRSplineDev), _c_i32, _vp, _vp, _vp]),
     "lr_render": (_c_i32, [ctypes.POINTER(SceneC), ctypes.POINTER(ViewC), _c_i32, _vp, _vp, _vp]),
+    "lr_render_scheduled": (_c_i32, [ctypes.POINTER(SceneC), ctypes.POINTER(ViewC), _c_i32, _vp, _vp, _vp, _c_i64,
+                                     _vp]),
+    "lr_render_workspace_size": (_c_i32, [ctypes.POINTER(ViewC), _c_i32, ctypes.POINTER(_c_i64)]),
     "lr_render_backward": (_c_i32, [ctypes.POINTER(SceneC), ctypes.POINTER(ViewC), _c_i32, _vp, _vp, _vp, _vp, _vp]),
     "lr_streamlines": (_c_i32, [ctypes.POINTER(SceneC), ctypes.POINTER(StreamParams), _vp, _c_i64, _vp, _vp, _vp,
                                 _vp]),

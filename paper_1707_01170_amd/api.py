@@ -304,9 +304,23 @@ class Scene:
         return s
 
 
-def render(scene: Scene, views: Sequence, bezier=None, lut=None, out=None, nsamples: bool = False):
+def render_workspace(views: Sequence, device) -> torch.Tensor:
+    """Device workspace for lr_render_scheduled over these views (256-byte aligned)."""
+    arr, _ = view_array(views)
+    n = ctypes.c_int64(0)
+    L.check(L.lib().lr_render_workspace_size(arr, len(views), ctypes.byref(n)))
+    ws = torch.empty(n.value + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + n.value]
+
+
+def render(scene: Scene, views: Sequence, bezier=None, lut=None, out=None, nsamples: bool = False,
+           schedule: bool = True, workspace: Optional[torch.Tensor] = None):
     """Render views into one packed RGBA tensor [sum W*H, 4] (float32).
-    Returns (rgba, offsets, nsamples or None)."""
+    Returns (rgba, offsets, nsamples or None).  schedule: deal the work
+    longest first from a per-launch cost estimate (lr_render_scheduled, in a
+    workspace from render_workspace or allocated here); otherwise from the
+    middle of each view outwards (lr_render).  The images are the same."""
     dev = scene.volume.device
     arr, offs = view_array(views)
     total = sum(v.width * v.height for v in views)
@@ -314,7 +328,12 @@ def render(scene: Scene, views: Sequence, bezier=None, lut=None, out=None, nsamp
         out = torch.empty((total, 4), dtype=torch.float32, device=dev)
     ns = torch.empty(total, dtype=torch.int32, device=dev) if nsamples else None
     s = scene.struct(bezier, lut)
-    L.check(L.lib().lr_render(ctypes.byref(s), arr, len(views), _ptr(out), _ptr(ns), _stream(dev)))
+    if schedule:
+        ws = render_workspace(views, dev) if workspace is None else workspace
+        L.check(L.lib().lr_render_scheduled(ctypes.byref(s), arr, len(views), _ptr(out), _ptr(ns), _ptr(ws),
+                                            ws.numel() * ws.element_size(), _stream(dev)))
+    else:
+        L.check(L.lib().lr_render(ctypes.byref(s), arr, len(views), _ptr(out), _ptr(ns), _stream(dev)))
     return out, offs, ns
 
 

@@ -57,6 +57,7 @@ struct ViewsK {
   int64_t quad_base[kMaxViews + 1];    // prefix sums of kQuad x kQuad blocks of tiles
   int32_t quads_x[kMaxViews];
   int32_t n;
+  const int32_t* order;                // per view, its blocks by decreasing estimated cost; null: ring order
 };
 
 struct Ray {
@@ -452,7 +453,13 @@ __device__ inline bool locate(const ViewsK& vk, int64_t b, int& v, int& px, int&
   const int64_t lq = q - vk.quad_base[v];
   const int qw = vk.quads_x[v], qh = (int)((vk.quad_base[v + 1] - vk.quad_base[v]) / qw);
   int qx, qy;
-  ring_cell(lq, qw, qh, qx, qy);
+  if (vk.order) {
+    const int32_t o = vk.order[vk.quad_base[v] + lq];
+    qx = o % qw;
+    qy = o / qw;
+  } else {
+    ring_cell(lq, qw, qh, qx, qy);
+  }
   const int gx = qx * kQuad + w % kQuad;
   const int gy = qy * kQuad + w / kQuad;
   const int lane = threadIdx.x & 63;
@@ -573,6 +580,93 @@ __global__ void lookup_octree_kernel(const uint32_t* __restrict__ root, const ui
   float p[3];
   for (int a = 0; a < 3; ++a) p[a] = fminf(fmaxf(pts[3 * k + a], 0.0f), 1.0f);
   out[k] = octree_lookup(root, nodes, n_nodes, n_elem, p);
+}
+
+// ---------------------------------------------------------------- dispatch order
+// The samples a ray takes follow from the element sizes along it (Eq. 4), so
+// a block's cost is estimated before the render: half a wavefront per block of
+// tiles, 32 points evenly spaced along the block's centre ray, each adding
+// its stretch of the ray divided by the smallest side of the element there.
+// The blocks of each view are then ranked by decreasing estimate (a counting
+// sort on 64 levels, one workgroup per view) and the render deals them in
+// that order: the longest rays start first, whatever the shape of the dense
+// region in the image.  The order changes no pixel; blocks of one level are
+// ordered arbitrarily.
+template <int LK>
+__global__ __launch_bounds__(64) void quad_cost_kernel(const SceneK s, const ViewsK vk, int fixed,
+                                                       float* __restrict__ cost) {
+  const int half = threadIdx.x >> 5, lane = threadIdx.x & 31;
+  const int64_t q = 2 * (int64_t)blockIdx.x + half;
+  const bool valid = q < vk.quad_base[vk.n];
+  float c = 0.0f;
+  if (valid) {
+    int v = 0;
+    while (v + 1 < vk.n && q >= vk.quad_base[v + 1]) ++v;
+    const int64_t lq = q - vk.quad_base[v];
+    const int qw = vk.quads_x[v];
+    const int qx = (int)(lq % qw), qy = (int)(lq / qw);
+    const lr_view& view = vk.v[v];
+    constexpr int kSpan = kQuad * kGroup;
+    const int px = min(qx * kSpan + kSpan / 2, view.width - 1);
+    const int py = min(qy * kSpan + kSpan / 2, view.height - 1);
+    const Ray r = make_ray(view, px, py);
+    if (r.hit) {
+      const float len = r.t1 - r.t0;
+      if (fixed) {
+        c = lane == 0 ? (float)s.n_fixed : 0.0f;
+      } else {
+        float p[3];
+        position(r, r.t0 + ((float)lane + 0.5f) * (len * (1.0f / 32.0f)), p);
+        const int32_t e = find_element<LK>(s, p);
+        if (e >= 0) {
+          const float* b = s.box + 6 * (int64_t)e;
+          const float side = fminf(fminf(b[3] - b[0], b[4] - b[1]), b[5] - b[2]);
+          c = side > 0.0f ? len * (1.0f / 32.0f) / side : 0.0f;
+        }
+      }
+    }
+  }
+  for (int off = 16; off > 0; off >>= 1) c += __shfl_xor(c, off);   // within each half
+  if (valid && lane == 0) cost[q] = c >= 0.0f ? c : 0.0f;
+}
+
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderLevels = 64;
+
+__global__ __launch_bounds__(kOrderThreads) void quad_order_kernel(const ViewsK vk, const float* __restrict__ cost,
+                                                                   int32_t* __restrict__ order) {
+  __shared__ float wmax[kOrderThreads / 64];
+  __shared__ int32_t first[kOrderLevels];
+  const int v = blockIdx.x, tid = threadIdx.x;
+  const int64_t base = vk.quad_base[v];
+  const int n = (int)(vk.quad_base[v + 1] - base);
+  float m = 0.0f;
+  for (int i = tid; i < n; i += kOrderThreads) m = fmaxf(m, cost[base + i]);
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  if ((tid & 63) == 0) wmax[tid >> 6] = m;
+  if (tid < kOrderLevels) first[tid] = 0;
+  __syncthreads();
+  float mx = 0.0f;
+  for (int w = 0; w < kOrderThreads / 64; ++w) mx = fmaxf(mx, wmax[w]);
+  const float scale = mx > 0.0f ? (float)(kOrderLevels - 1) / mx : 0.0f;
+  auto level = [&](float c) {   // 0 for the costliest blocks
+    int l = (int)(c * scale);
+    l = l < 0 ? 0 : (l > kOrderLevels - 1 ? kOrderLevels - 1 : l);
+    return kOrderLevels - 1 - l;
+  };
+  for (int i = tid; i < n; i += kOrderThreads) atomicAdd(&first[level(cost[base + i])], 1);
+  __syncthreads();
+  if (tid < kOrderLevels) {   // one wavefront: exclusive scan of the level counts
+    const int own = first[tid];
+    int x = own;
+    for (int off = 1; off < kOrderLevels; off <<= 1) {
+      const int y = __shfl_up(x, off);
+      if (tid >= off) x += y;
+    }
+    first[tid] = x - own;
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += kOrderThreads) order[base + atomicAdd(&first[level(cost[base + i])], 1)] = i;
 }
 
 // ---------------------------------------------------------------- adjoint
@@ -1019,29 +1113,98 @@ void dispatch_trace(const lr_scene* sc, const SceneK& s, const lr_view& v, const
 
 using lrvr::fail;
 
-LR_API lr_status lr_render(const lr_scene* sc, const lr_view* views, int32_t n_views, float* rgba, uint32_t* nsamples,
-                           void* stream) {
+// Bytes of the dispatch-order workspace for one launch of nq blocks: the
+// estimates, then the order, each 256-byte aligned.
+static int64_t order_bytes(int64_t nq) { return 2 * ((nq * 4 + 255) / 256 * 256); }
+
+// Largest workspace any launch of these views needs (views in launches of
+// kMaxViews); -1 if a launch would be too large.
+static int64_t order_workspace(const lr_view* views, int32_t n_views) {
+  int64_t need = 0;
+  for (int base = 0; base < n_views; base += kMaxViews) {
+    const int cnt = n_views - base < kMaxViews ? n_views - base : kMaxViews;
+    ViewsK vk;
+    const int64_t nblk = pack_views(views + base, cnt, vk);
+    if (nblk <= 0 || nblk > 0x7fffffff) return -1;
+    const int64_t b = order_bytes(vk.quad_base[cnt]);
+    need = b > need ? b : need;
+  }
+  return need;
+}
+
+// Estimates the blocks' costs and ranks them into ws (order_bytes of the
+// launch's blocks), and points vk at the order.
+static void schedule(const lr_scene* sc, const SceneK& s, ViewsK& vk, void* ws, hipStream_t st) {
+  const int64_t nq = vk.quad_base[vk.n];
+  float* cost = static_cast<float*>(ws);
+  int32_t* order = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + order_bytes(nq) / 2);
+  const int fixed = sc->step_mode == LR_STEP_FIXED;
+  if (s.lookup == LR_LOOKUP_OCTREE)
+    hipLaunchKernelGGL(quad_cost_kernel<LR_LOOKUP_OCTREE>, dim3((unsigned)((nq + 1) / 2)), dim3(64), 0, st, s, vk,
+                       fixed, cost);
+  else
+    hipLaunchKernelGGL(quad_cost_kernel<LR_LOOKUP_FOREST>, dim3((unsigned)((nq + 1) / 2)), dim3(64), 0, st, s, vk,
+                       fixed, cost);
+  hipLaunchKernelGGL(quad_order_kernel, dim3((unsigned)vk.n), dim3(kOrderThreads), 0, st, vk, cost, order);
+  vk.order = order;
+}
+
+// lr_render and lr_render_scheduled: ws null deals the blocks in ring order.
+static lr_status render_views(const char* who, const lr_scene* sc, const lr_view* views, int32_t n_views,
+                              float* rgba, uint32_t* nsamples, void* ws, int64_t ws_bytes, void* stream) {
   SceneK s;
   lr_status st = make_scene(sc, s);
   if (st != LR_OK) return st;
-  if (!views || n_views < 1 || !rgba) return fail(LR_EINVAL, "lr_render: need views, n_views >= 1 and rgba");
+  if (!views || n_views < 1 || !rgba) return fail(LR_EINVAL, "%s: need views, n_views >= 1 and rgba", who);
   for (int i = 0; i < n_views; ++i)
     if ((st = check_view(views[i])) != LR_OK) return st;
+  if (ws) {
+    const int64_t need = order_workspace(views, n_views);
+    if (need < 0) return fail(LR_EINVAL, "%s: image too large for one launch", who);
+    if (ws_bytes < need)
+      return fail(LR_ECAPACITY, "%s: workspace of %lld bytes, the views need %lld", who, (long long)ws_bytes,
+                  (long long)need);
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(LR_EINVAL, "%s: workspace not 256-byte aligned", who);
+  }
   hipStream_t hs = static_cast<hipStream_t>(stream);
   for (int base = 0; base < n_views; base += kMaxViews) {
     const int cnt = n_views - base < kMaxViews ? n_views - base : kMaxViews;
     ViewsK vk;
     const int64_t nblk = pack_views(views + base, cnt, vk);
-    if (nblk <= 0 || nblk > 0x7fffffff) return fail(LR_EINVAL, "lr_render: image too large for one launch");
+    if (nblk <= 0 || nblk > 0x7fffffff) return fail(LR_EINVAL, "%s: image too large for one launch", who);
+    if (ws) schedule(sc, s, vk, ws, hs);
     switch (sc->p[0]) {
       case 1: dispatch_render<1>(sc, s, vk, nblk, rgba, nsamples, hs); break;
       case 2: dispatch_render<2>(sc, s, vk, nblk, rgba, nsamples, hs); break;
       default: dispatch_render<3>(sc, s, vk, nblk, rgba, nsamples, hs); break;
     }
     hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return fail(LR_EHIP, "lr_render: %s", hipGetErrorString(err));
+    if (err != hipSuccess) return fail(LR_EHIP, "%s: %s", who, hipGetErrorString(err));
   }
   return LR_OK;
+}
+
+LR_API lr_status lr_render(const lr_scene* sc, const lr_view* views, int32_t n_views, float* rgba, uint32_t* nsamples,
+                           void* stream) {
+  return render_views("lr_render", sc, views, n_views, rgba, nsamples, nullptr, 0, stream);
+}
+
+LR_API lr_status lr_render_workspace_size(const lr_view* views, int32_t n_views, int64_t* bytes) {
+  if (!views || n_views < 1 || !bytes) return fail(LR_EINVAL, "lr_render_workspace_size: need views and bytes");
+  for (int i = 0; i < n_views; ++i) {
+    const lr_status st = check_view(views[i]);
+    if (st != LR_OK) return st;
+  }
+  const int64_t need = order_workspace(views, n_views);
+  if (need < 0) return fail(LR_EINVAL, "lr_render_workspace_size: image too large for one launch");
+  *bytes = need;
+  return LR_OK;
+}
+
+LR_API lr_status lr_render_scheduled(const lr_scene* sc, const lr_view* views, int32_t n_views, float* rgba,
+                                     uint32_t* nsamples, void* workspace, int64_t workspace_bytes, void* stream) {
+  if (!workspace) return fail(LR_EINVAL, "lr_render_scheduled: null workspace");
+  return render_views("lr_render_scheduled", sc, views, n_views, rgba, nsamples, workspace, workspace_bytes, stream);
 }
 
 LR_API lr_status lr_trace_rays(const lr_scene* sc, const lr_view* view, const int32_t* pix, int64_t n, int32_t max_out,

@@ -434,3 +434,34 @@ def test_header_is_plain_c(tmp_path):
     want = [ctypes.sizeof(L.SceneC), ctypes.sizeof(L.ViewC), ctypes.sizeof(L.LRSplineDev), ctypes.sizeof(L.KdNode),
             ctypes.sizeof(L.ForestStats), ctypes.sizeof(L.StreamParams), L.SceneC.shading.offset, L.SceneC.lookup.offset]
     assert got == want
+
+
+def test_render_workspace_size():
+    """Host-only query of lr_render_scheduled's workspace: 8 bytes per
+    16x16-pixel block of the largest launch (16 views per launch), each half
+    rounded up to 256 bytes; bad views are errors."""
+    from paper_1707_01170_amd.api import view_array
+    n = ctypes.c_int64(0)
+
+    def size(views):
+        arr, _ = view_array(views)
+        st = L.lib().lr_render_workspace_size(arr, len(views), ctypes.byref(n))
+        return st, n.value
+
+    def expect(views):
+        per_launch = []
+        for k in range(0, len(views), 16):
+            q = sum(((v.width + 15) // 16) * ((v.height + 15) // 16) for v in views[k:k + 16])
+            per_launch.append(2 * ((q * 4 + 255) // 256 * 256))
+        return max(per_launch)
+
+    v = lrgen.sphere_view(np.array([1.0, 0.2, 0.3]), 1920, 1080)
+    assert size([v]) == (L.LR_OK, 65536) == (L.LR_OK, expect([v]))
+    rng = np.random.default_rng(2)
+    views = [lrgen.sphere_view(lrgen.random_directions(rng, 1)[0], int(w), int(h))
+             for w, h in rng.integers(1, 700, size=(21, 2))]
+    assert size(views) == (L.LR_OK, expect(views))
+    bad = lrgen.sphere_view(np.array([1.0, 0.0, 0.0]), 64, 64)
+    bad.width = 0
+    assert size([bad])[0] == L.LR_EINVAL
+    assert L.lib().lr_render_workspace_size(None, 1, ctypes.byref(n)) == L.LR_EINVAL

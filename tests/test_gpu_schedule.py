@@ -1,0 +1,91 @@
+"""Cost-ordered dispatch (lr_render_scheduled): the order in which blocks of
+tiles are dealt changes no pixel, so every render equals lr_render's bit for
+bit, including the per-pixel sample counts, for single and multi-launch view
+sets, both look-up structures, fixed and adaptive steps, FP16 blocks and
+shading; a too-small, null or misaligned workspace is an error."""
+import ctypes
+import dataclasses
+
+import pytest
+import torch
+
+import lrgen
+from conftest import workload
+from gpu_util import resized, say, scene
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _both(sc, views, **kw):
+    import paper_1707_01170_amd as P
+    total = sum(v.width * v.height for v in views)
+    outs = []
+    for schedule in (False, True):
+        out = torch.full((total, 4), -7.0, device="cuda:0")   # a pixel left unwritten would keep -7
+        _, _, ns = P.render(sc, views, out=out, nsamples=True, schedule=schedule, **kw)
+        outs.append((out, ns))
+    torch.cuda.synchronize()
+    (a, na), (b, nb) = outs
+    return a, b, na, nb
+
+
+@pytest.mark.parametrize("name,blocks,dtype,shading", [("vortex200k", 256, "f32", "none"),
+                                                       ("vortex200k", 256, "f16", "headlight"),
+                                                       ("blobs50k", 128, "f16", "none"),
+                                                       ("scalar20k", 64, "f32", "none"),
+                                                       ("scalar_ortho64", 16, "f32", "none")])
+def test_scheduled_equals_ring_order(name, blocks, dtype, shading):
+    import paper_1707_01170_amd as P
+    say("[gpu] scheduled dispatch", name, blocks, dtype, shading)
+    wl, sc = scene(name, blocks=blocks, dtype=dtype)
+    if shading != "none":
+        sc = P.Scene(sc.volume, dataclasses.replace(P.RenderParams.of(wl), shading=shading))
+    a, b, na, nb = _both(sc, wl.views)
+    say("%s: %d views, %d samples" % (name, len(wl.views), int(nb.sum())))
+    assert bool((a != -7.0).all())
+    assert torch.equal(a, b) and torch.equal(na, nb)
+
+
+def test_scheduled_octree_and_many_views():
+    """The octree look-up; 20 views of mixed sizes, so two launches reuse one workspace."""
+    import paper_1707_01170_amd as P
+    say("[gpu] scheduled dispatch, octree, 20 views")
+    wl = workload("blobs50k")
+    vol = P.Volume(wl.spline, lookup="octree", device="cuda:0")
+    sc = P.Scene(vol, P.RenderParams.of(wl))
+    import numpy as np
+    rng = np.random.default_rng(5)
+    dirs = lrgen.random_directions(rng, 20)
+    sizes = [(40, 28), (96, 96), (200, 64), (17, 33), (128, 200)]
+    views = [lrgen.sphere_view(dirs[k], *sizes[k % len(sizes)]) for k in range(20)]
+    a, b, na, nb = _both(sc, views)
+    assert bool((a != -7.0).all())
+    assert torch.equal(a, b) and torch.equal(na, nb)
+
+
+def test_workspace_errors():
+    import paper_1707_01170_amd as P
+    from paper_1707_01170_amd import _lib as L
+    from paper_1707_01170_amd.api import _ptr, _stream, view_array
+    say("[gpu] scheduled dispatch, workspace errors")
+    wl, sc = scene("scalar20k")
+    views = [resized(wl.views[0], 64, 48)]
+    ws = P.render_workspace(views, "cuda:0")
+    arr, _ = view_array(views)
+    out = torch.empty((64 * 48, 4), device="cuda:0")
+    s = sc.struct()
+    lib = L.lib()
+    n = ws.numel()
+    assert lib.lr_render_scheduled(ctypes.byref(s), arr, 1, _ptr(out), None, _ptr(ws), n - 1, _stream()) == L.LR_ECAPACITY
+    assert lib.lr_render_scheduled(ctypes.byref(s), arr, 1, _ptr(out), None, None, n, _stream()) == L.LR_EINVAL
+    big = torch.empty(n + 512, dtype=torch.uint8, device="cuda:0")
+    base = big[(-big.data_ptr()) % 256:]
+    assert lib.lr_render_scheduled(ctypes.byref(s), arr, 1, _ptr(out), None, base.data_ptr() + 4, n, _stream()) == L.LR_EINVAL
+    assert lib.lr_render_scheduled(ctypes.byref(s), arr, 1, _ptr(out), None, _ptr(ws), n, _stream()) == L.LR_OK
+    torch.cuda.synchronize()
