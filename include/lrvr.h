@@ -322,6 +322,16 @@ lr_status lr_render_scheduled(const lr_scene* sc, const lr_view* views, int32_t 
                               uint32_t* nsamples, void* workspace, int64_t workspace_bytes,
                               void* stream);
 
+/* lr_render_scheduled for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid it): the
+ * workspace is a 2 MiB array the library holds on each GPU it runs on, until
+ * the process ends, so no call allocates.  At most 262 144 blocks of 16x16
+ * pixels per launch of up to 16 views (16 views of 2048^2); larger requests
+ * return LR_ECAPACITY and render nothing.  Calls that overlap on one GPU
+ * share the array and race: serialise them (one stream, or events). */
+lr_status lr_render_scheduled_noalloc(const lr_scene* sc, const lr_view* views, int32_t n_views,
+                                      float* rgba, uint32_t* nsamples, void* stream);
+
 /* Bytes of workspace lr_render_scheduled needs for these views (host only,
  * no GPU work): 8 bytes per 16x16-pixel block of the largest launch (16
  * views per launch), each half rounded up to 256.  LR_EINVAL for null

@@ -86,6 +86,7 @@ SIGNATURES = {
     "lr_render_scheduled": (_c_i32, [ctypes.POINTER(SceneC), ctypes.POINTER(ViewC), _c_i32, _vp, _vp, _vp, _c_i64,
                                      _vp]),
     "lr_render_workspace_size": (_c_i32, [ctypes.POINTER(ViewC), _c_i32, ctypes.POINTER(_c_i64)]),
+    "lr_render_scheduled_noalloc": (_c_i32, [ctypes.POINTER(SceneC), ctypes.POINTER(ViewC), _c_i32, _vp, _vp, _vp]),
     "lr_render_backward": (_c_i32, [ctypes.POINTER(SceneC), ctypes.POINTER(ViewC), _c_i32, _vp, _vp, _vp, _vp, _vp]),
     "lr_streamlines": (_c_i32, [ctypes.POINTER(SceneC), ctypes.POINTER(StreamParams), _vp, _c_i64, _vp, _vp, _vp,
                                 _vp]),

@@ -18,6 +18,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -1187,6 +1188,54 @@ static lr_status render_views(const char* who, const lr_scene* sc, const lr_view
 LR_API lr_status lr_render(const lr_scene* sc, const lr_view* views, int32_t n_views, float* rgba, uint32_t* nsamples,
                            void* stream) {
   return render_views("lr_render", sc, views, n_views, rgba, nsamples, nullptr, 0, stream);
+}
+
+// Dispatch-order scratch of lr_render_scheduled_noalloc: one array per GPU,
+// held until the process ends, for callers that cannot allocate.  Host code
+// uses only the device address hipGetSymbolAddress gives for it (per device,
+// on that device's first call); the array's name is no device address on the
+// host.  Calls that overlap on one GPU share the array and race.
+constexpr int64_t kScheduleScratchBytes = (int64_t)2 << 20;   // 262 144 blocks of 16x16 pixels per launch
+static __device__ __align__(256) unsigned char scratch[kScheduleScratchBytes];
+static std::mutex g_scratch_mutex;
+static void* g_scratch[256];   // per device id
+
+static lr_status scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(LR_EHIP, "lr_render_scheduled_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= 256) return fail(LR_EINVAL, "lr_render_scheduled_noalloc: device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(LR_EHIP, "lr_render_scheduled_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return LR_OK;
+}
+
+LR_API lr_status lr_render_scheduled_noalloc(const lr_scene* sc, const lr_view* views, int32_t n_views, float* rgba,
+                                             uint32_t* nsamples, void* stream) {
+  if (!views || n_views < 1) return fail(LR_EINVAL, "lr_render_scheduled_noalloc: need views and n_views >= 1");
+  for (int i = 0; i < n_views; ++i) {
+    const lr_status st = check_view(views[i]);
+    if (st != LR_OK) return st;
+  }
+  const int64_t need = order_workspace(views, n_views);
+  if (need < 0) return fail(LR_EINVAL, "lr_render_scheduled_noalloc: image too large for one launch");
+  if (need > kScheduleScratchBytes)
+    return fail(LR_ECAPACITY,
+                "lr_render_scheduled_noalloc: a launch of these views needs %lld bytes of dispatch-order scratch; "
+                "the library holds %lld (262 144 blocks of 16x16 pixels per launch of up to 16 views)",
+                (long long)need, (long long)kScheduleScratchBytes);
+  void* ws = nullptr;
+  const lr_status st = scratch_address(&ws);
+  if (st != LR_OK) return st;
+  return render_views("lr_render_scheduled_noalloc", sc, views, n_views, rgba, nsamples, ws, kScheduleScratchBytes,
+                      stream);
 }
 
 LR_API lr_status lr_render_workspace_size(const lr_view* views, int32_t n_views, int64_t* bytes) {
