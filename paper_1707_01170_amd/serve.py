@@ -92,7 +92,8 @@ class ServeStats:
 
 class Server:
     def __init__(self, scene: Scene, budget_bytes: int = 1 << 30, n_streams: int = 3,
-                 max_views: int = L.LR_MAX_VIEWS_PER_LAUNCH, max_pixels_per_launch: int = 1 << 24):
+                 max_views: int = L.LR_MAX_VIEWS_PER_LAUNCH, max_pixels_per_launch: int = 1 << 24,
+                 schedule: bool = False):
         dev = scene.volume.device
         self.scene = scene
         self.arena = Arena(budget_bytes // 16, dev)
@@ -100,6 +101,18 @@ class Server:
         self.streams = [torch.cuda.Stream(device=dev) for _ in range(n_streams)]
         self.max_views = max_views
         self.max_px = max_pixels_per_launch
+        # schedule: launches deal their blocks longest first (lr_render_scheduled), in a
+        # workspace per stream (one launch in flight per stream) for the largest launch:
+        # max_views views of max_pixels_per_launch pixels in all, in blocks of 16x16
+        self.workspaces = None
+        if schedule:
+            blocks = max_pixels_per_launch // 256 + max_views * (2 * ((max_pixels_per_launch ** 0.5) // 16 + 2) + 1)
+            nbytes = 2 * (int(blocks) * 4 + 255) // 256 * 256
+            self.workspaces = []
+            for _ in range(n_streams):
+                ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+                off = (-ws.data_ptr()) % 256
+                self.workspaces.append(ws[off:off + nbytes])
 
     def run(self, requests: Sequence, keep_images: bool = False, time_scale: float = 1.0) -> ServeStats:
         """Serve requests (objects with .arrival_s and .view) in real time.
@@ -151,8 +164,13 @@ class Server:
                 with torch.cuda.stream(self.streams[si]):
                     arr = _view_array_at(views, [off for _, off in batch])
                     s = self.scene.struct()
-                    L.check(L.lib().lr_render(_byref(s), arr, len(views), _ptr(self.arena.buf), None,
-                                              _stream_handle(self.streams[si])))
+                    if self.workspaces is None:
+                        L.check(L.lib().lr_render(_byref(s), arr, len(views), _ptr(self.arena.buf), None,
+                                                  _stream_handle(self.streams[si])))
+                    else:
+                        ws = self.workspaces[si]
+                        L.check(L.lib().lr_render_scheduled(_byref(s), arr, len(views), _ptr(self.arena.buf), None,
+                                                            _ptr(ws), ws.numel(), _stream_handle(self.streams[si])))
                     ev = torch.cuda.Event(enable_timing=True)
                     ev.record(self.streams[si])
                 for k, _ in batch:

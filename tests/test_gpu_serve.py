@@ -29,16 +29,18 @@ def _stream(n, seed, sizes=(40, 64, 96, 128, 200)):
             for k in range(n)]
 
 
-@pytest.mark.parametrize("dtype,time_scale", [("f32", 1.0), ("f16", 1.0), ("f32", 0.0), ("f16", 0.05)])
-def test_results_identical_alone_and_in_the_mix(dtype, time_scale):
+@pytest.mark.parametrize("dtype,time_scale,schedule", [("f32", 1.0, False), ("f16", 1.0, False), ("f32", 0.0, False),
+                                                       ("f16", 0.05, False), ("f16", 0.0, True)])
+def test_results_identical_alone_and_in_the_mix(dtype, time_scale, schedule):
     """Each request's image is the same bits alone and batched with others;
     time_scale compresses the arrivals (0: all at once), so that requests
-    queue and launches carry several views."""
+    queue and launches carry several views; schedule: launches dealt by cost
+    estimate (lr_render_scheduled, one workspace per stream)."""
     from paper_1707_01170_amd.serve import Server, render_alone
-    say("[gpu] serve mix", dtype, time_scale)
+    say("[gpu] serve mix", dtype, time_scale, schedule)
     _, sc = scene("blobs50k", dtype=dtype)
     reqs = _stream(60, 1)
-    srv = Server(sc, budget_bytes=16 * 200 * 200 * 6, n_streams=3)
+    srv = Server(sc, budget_bytes=16 * 200 * 200 * 6, n_streams=3, schedule=schedule)
     st = srv.run(reqs, keep_images=True, time_scale=time_scale)
     assert st.n == 60 and st.launches < 60 and st.max_inflight >= 1
     if time_scale == 0.0:
