@@ -278,6 +278,54 @@ def lookup_sweep(dev, name: str, steps: int = 10):
             "rows": rows}
 
 
+def dispatch_study(dev, name: str, steps: int = 20, blocks: int = 256):
+    """Frame time of one view under each way of handing its tiles to the GPU:
+    the hardware's dispatch of one workgroup per tile (ring order: lr_render;
+    longest first: lr_render_scheduled) against persistent workgroups taking
+    tiles from one atomic counter or from one per XCD (lr_render_persistent),
+    in either order.  Every form renders the identical image."""
+    import torch
+
+    import lrgen
+    import paper_1707_01170_amd as P
+    wl = lrgen.cached(name)
+    vol = P.Volume(wl.spline, blocks=blocks, device=dev)
+    sc = P.Scene(vol, P.RenderParams.of(wl))
+    view = wl.views[0]
+    ws = P.render_workspace([view], dev)
+    out = torch.empty((view.width * view.height, 4), dtype=torch.float32, device=dev)
+    forms = [("hardware dispatch, ring order", dict(schedule=False)),
+             ("hardware dispatch, longest first", dict(schedule=True)),
+             ("1 queue, ring order", dict(schedule=False, queues=1)),
+             ("1 queue, longest first", dict(schedule=True, queues=1)),
+             ("8 queues (one per XCD), ring order", dict(schedule=False, queues=8)),
+             ("8 queues (one per XCD), longest first", dict(schedule=True, queues=8))]
+    rows, ref = [], None
+    for label, kw in forms:
+        P.render(sc, [view], out=out, workspace=ws, **kw)
+        torch.cuda.synchronize()
+        same = None
+        if ref is None:
+            ref = out.clone()
+        else:
+            same = bool(torch.equal(out, ref))
+        for _ in range(2):
+            P.render(sc, [view], out=out, workspace=ws, **kw)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            P.render(sc, [view], out=out, workspace=ws, **kw)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        log("dispatch study %s %-40s %8.3f ms  identical %s" % (name, label, ms, same))
+        rows.append({"form": label, "ms_per_frame": ms, "image_identical_to_first": same})
+    del vol, sc, out, ws
+    torch.cuda.empty_cache()
+    return {"workload": "%s: %d elements, %dx%d view, forest %d^3, FP32 blocks"
+                        % (name, wl.spline.n_elem, view.width, view.height, blocks), "rows": rows}
+
+
 def _stream_seeds(n: int, seed: int = 3):
     rng = np.random.default_rng(seed)
     lo, hi = np.array([0.35, 0.35, 0.2]), np.array([0.65, 0.65, 0.8])
@@ -393,6 +441,8 @@ def main():
                     help="also compare every RK method / step rule / precision by the error metric Eq. 7")
     ap.add_argument("--lookup-sweep", action="store_true",
                     help="also time every look-up structure (forest sizes, octree) on the 1080p and blob workloads")
+    ap.add_argument("--dispatch-study", action="store_true",
+                    help="also time hardware dispatch against persistent work queues on the 1080p and blob workloads")
     ap.add_argument("--serve", type=int, default=1000,
                     help="requests of the serving stream on the blob volume with FP16 blocks (0: skip)")
     args = ap.parse_args()
@@ -513,6 +563,8 @@ def main():
     lines = stream_lines(sc, study=args.stream_study) if args.extras else None
     adjoint = adjoint_step(dev) if args.adjoint else None
     sweep = [lookup_sweep(dev, n) for n in ("vortex200k", "blobs50k")] if args.lookup_sweep else None
+    study = ([dispatch_study(dev, "vortex200k", blocks=256), dispatch_study(dev, "blobs50k", blocks=128)]
+             if args.dispatch_study else None)
     serving = None
     if args.serve > 0:
         serving = serve_stream(args.serve, dev)
@@ -560,6 +612,8 @@ def main():
     }
     if sweep is not None:
         res["lookup_sweep"] = sweep
+    if study is not None:
+        res["dispatch_study"] = study
     print(json.dumps(res), flush=True)
 
 

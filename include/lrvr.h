@@ -310,7 +310,7 @@ lr_status lr_render(const lr_scene* sc, const lr_view* views, int32_t n_views, f
  * for bit, and the same errors, in less time when the work per pixel is
  * uneven.  A launch's blocks of 16x16 pixels are dealt to the GPU longest
  * first; a block's cost is estimated from the element sizes (Eq. 4 steps) at
- * 64 points along its centre ray, and lr_render instead deals the blocks from
+ * 32 points along its centre ray, and lr_render instead deals the blocks from
  * the middle of each view outwards.
  * workspace        device memory, 256-byte aligned, of at least the bytes
  *                  lr_render_workspace_size returns for the same views; the
@@ -337,6 +337,28 @@ lr_status lr_render_scheduled_noalloc(const lr_scene* sc, const lr_view* views, 
  * views per launch), each half rounded up to 256.  LR_EINVAL for null
  * arguments or invalid views. */
 lr_status lr_render_workspace_size(const lr_view* views, int32_t n_views, int64_t* bytes);
+
+/* lr_render through persistent workgroups that take the launch's 8x8-pixel
+ * tiles from atomic counters in device memory: the same images, bit for bit,
+ * and the same errors.  It is the form of work distribution the hardware's
+ * own dispatch replaces in lr_render and lr_render_scheduled (faster on this
+ * GPU); it is kept so that the two can be compared.  Forest look-up without
+ * shading only (LR_EINVAL otherwise).
+ * queues           1: one counter hands out the tiles in dealing order to
+ *                  whichever workgroup asks; 8: one counter per XCD, shared
+ *                  by the workgroups the hardware deals to that XCD, handing
+ *                  out the tiles lr_render renders there
+ * cost_order       0: tiles dealt from the middle of each view outwards, as
+ *                  lr_render; 1: longest first, as lr_render_scheduled
+ * workgroups       single-wave workgroups to start, at most 2^20; 0: as many
+ *                  as the GPU holds at once; rounded up to a multiple of 8
+ * workspace, workspace_bytes
+ *                  as for lr_render_scheduled (lr_render_workspace_size
+ *                  bytes, 256-byte aligned, owned by the caller); the
+ *                  counters live in its first 256 bytes */
+lr_status lr_render_persistent(const lr_scene* sc, const lr_view* views, int32_t n_views, float* rgba,
+                               uint32_t* nsamples, int32_t queues, int32_t cost_order, int32_t workgroups,
+                               void* workspace, int64_t workspace_bytes, void* stream);
 
 /* Adjoint of lr_render for scalar fields (ncomp 1, LR_COLOR_LUT, F32 blocks,
  * either look-up structure, no shading).

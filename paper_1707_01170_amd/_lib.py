@@ -87,6 +87,8 @@ SIGNATURES = {
                                      _vp]),
     "lr_render_workspace_size": (_c_i32, [ctypes.POINTER(ViewC), _c_i32, ctypes.POINTER(_c_i64)]),
     "lr_render_scheduled_noalloc": (_c_i32, [ctypes.POINTER(SceneC), ctypes.POINTER(ViewC), _c_i32, _vp, _vp, _vp]),
+    "lr_render_persistent": (_c_i32, [ctypes.POINTER(SceneC), ctypes.POINTER(ViewC), _c_i32, _vp, _vp, _c_i32, _c_i32,
+                                      _c_i32, _vp, _c_i64, _vp]),
     "lr_render_backward": (_c_i32, [ctypes.POINTER(SceneC), ctypes.POINTER(ViewC), _c_i32, _vp, _vp, _vp, _vp, _vp]),
     "lr_streamlines": (_c_i32, [ctypes.POINTER(SceneC), ctypes.POINTER(StreamParams), _vp, _c_i64, _vp, _vp, _vp,
                                 _vp]),

@@ -315,12 +315,16 @@ def render_workspace(views: Sequence, device) -> torch.Tensor:
 
 
 def render(scene: Scene, views: Sequence, bezier=None, lut=None, out=None, nsamples: bool = False,
-           schedule: bool = True, workspace: Optional[torch.Tensor] = None):
+           schedule: bool = True, workspace: Optional[torch.Tensor] = None, queues: int = 0,
+           workgroups: int = 0):
     """Render views into one packed RGBA tensor [sum W*H, 4] (float32).
     Returns (rgba, offsets, nsamples or None).  schedule: deal the work
     longest first from a per-launch cost estimate (lr_render_scheduled, in a
     workspace from render_workspace or allocated here); otherwise from the
-    middle of each view outwards (lr_render).  The images are the same."""
+    middle of each view outwards (lr_render).  queues 1 or 8: persistent
+    workgroups take the tiles from that many atomic counters instead of the
+    hardware's dispatch (lr_render_persistent, `workgroups` of them, 0 for as
+    many as the GPU holds).  The images are the same."""
     dev = scene.volume.device
     arr, offs = view_array(views)
     total = sum(v.width * v.height for v in views)
@@ -328,7 +332,12 @@ def render(scene: Scene, views: Sequence, bezier=None, lut=None, out=None, nsamp
         out = torch.empty((total, 4), dtype=torch.float32, device=dev)
     ns = torch.empty(total, dtype=torch.int32, device=dev) if nsamples else None
     s = scene.struct(bezier, lut)
-    if schedule:
+    if queues:
+        ws = render_workspace(views, dev) if workspace is None else workspace
+        L.check(L.lib().lr_render_persistent(ctypes.byref(s), arr, len(views), _ptr(out), _ptr(ns), queues,
+                                             int(schedule), workgroups, _ptr(ws), ws.numel() * ws.element_size(),
+                                             _stream(dev)))
+    elif schedule:
         ws = render_workspace(views, dev) if workspace is None else workspace
         L.check(L.lib().lr_render_scheduled(ctypes.byref(s), arr, len(views), _ptr(out), _ptr(ns), _ptr(ws),
                                             ws.numel() * ws.element_size(), _stream(dev)))

@@ -495,13 +495,17 @@ constexpr int defer_divisor() {
   return (SH || !std::is_same<CT, float>::value) ? 0 : 2;
 }
 
-template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK, int SH>
-__device__ __forceinline__ void render_tile(const SceneK& s, const ViewsK& vk, float4* __restrict__ rgba,
-                                            uint32_t* __restrict__ nsamples, float4* lut) {
+__device__ __forceinline__ void load_lut(const SceneK& s, float4* lut) {
   for (int i = threadIdx.x; i < 256; i += kThreads) lut[i] = s.lut[i];
   __syncthreads();
+}
+
+// Renders the tile of workgroup index b (see locate), one pixel per lane.
+template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK, int SH>
+__device__ __forceinline__ void render_block(const SceneK& s, const ViewsK& vk, int64_t b, float4* __restrict__ rgba,
+                                             uint32_t* __restrict__ nsamples, float4* lut) {
   int v, px, py;
-  if (!locate(vk, blockIdx.x, v, px, py)) return;
+  if (!locate(vk, b, v, px, py)) return;
   const lr_view& view = vk.v[v];
   const int64_t o = view.out_offset + (int64_t)py * view.width + px;
   const Ray r = make_ray(view, px, py);
@@ -518,8 +522,51 @@ template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK, int SH>
 __global__ __launch_bounds__(kThreads) void render_kernel(const SceneK s, const ViewsK vk, float4* __restrict__ rgba,
                                                          uint32_t* __restrict__ nsamples) {
   __shared__ float4 lut[lut_rows<P, NCOMP, CT>()];   // rows beyond 256 are reserved, never touched
-  render_tile<P, NCOMP, CT, MODE, COLOR, LK, SH>(s, vk, rgba, nsamples, lut);
+  load_lut(s, lut);
+  render_block<P, NCOMP, CT, MODE, COLOR, LK, SH>(s, vk, blockIdx.x, rgba, nsamples, lut);
 }
+
+// Persistent form of the same launch, kept to compare work queues with the
+// hardware's dispatch (which is faster here): a grid of resident single-wave
+// workgroups takes workgroup indices b from atomic counters and renders tile
+// b as workgroup b of render_kernel would, so the image is the same bit for
+// bit.  With one counter the indices go out in order to whichever workgroup
+// asks; with one counter per XCD, the workgroups g with g mod 8 = x (those the
+// hardware deals to XCD x) share the indices b = x, x + 8, ..., the tiles
+// workgroup b of render_kernel would render on that XCD.  Counters are 32
+// bytes apart and zero at launch; each wave leaves once its counter has passed
+// its last index, so the grid drains whatever its size (at least 8 with one
+// counter per XCD, so that every counter has workgroups).  The loop holds a
+// few more registers; the degree-2 vector kernel is held to render_kernel's 4
+// waves per SIMD (128 VGPRs) so that the two differ in dispatch alone.
+template <int P, int NCOMP, typename CT>
+constexpr int queue_waves() {
+  return (P == 2 && NCOMP == 3 && sizeof(CT) == 4) ? 4 : 1;
+}
+
+template <int P, int NCOMP, typename CT, int MODE, int COLOR>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(queue_waves<P, NCOMP, CT>())))
+void render_queue_kernel(const SceneK s, const ViewsK vk,
+                                                               float4* __restrict__ rgba,
+                                                               uint32_t* __restrict__ nsamples,
+                                                               uint32_t* __restrict__ queue, int per_xcd,
+                                                               uint32_t nblk) {
+  __shared__ float4 lut[lut_rows<P, NCOMP, CT>()];
+  load_lut(s, lut);
+  const uint32_t x = per_xcd ? blockIdx.x & 7u : 0u;
+  const uint32_t stride = per_xcd ? 8u : 1u;
+  const uint32_t items = nblk / stride;   // nblk is a multiple of 8
+  for (;;) {
+    uint32_t item = 0;
+    if (threadIdx.x == 0) item = atomicAdd(&queue[8 * x], 1u);
+    item = __shfl(item, 0);
+    if (item >= items) break;
+    render_block<P, NCOMP, CT, MODE, COLOR, LR_LOOKUP_FOREST, 0>(s, vk, (int64_t)item * stride + x, rgba, nsamples,
+                                                                 lut);
+  }
+}
+
+__global__ __launch_bounds__(64) void queue_reset_kernel(uint32_t* __restrict__ queue) { queue[threadIdx.x] = 0u; }
 
 // The illuminated degree-2 vector kernel keeps the block, the value and three
 // derivatives of each component live: 173-175 VGPRs, 2 waves per SIMD.
@@ -536,7 +583,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
 void render_lit_vector2_kernel(const SceneK s, const ViewsK vk, float4* __restrict__ rgba,
                                uint32_t* __restrict__ nsamples) {
   __shared__ float4 lut[256];
-  render_tile<2, 3, CS, MODE, LR_COLOR_HUE, LR_LOOKUP_FOREST, 1>(s, vk, rgba, nsamples, lut);
+  load_lut(s, lut);
+  render_block<2, 3, CS, MODE, LR_COLOR_HUE, LR_LOOKUP_FOREST, 1>(s, vk, blockIdx.x, rgba, nsamples, lut);
 }
 
 template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK, int SH>
@@ -1075,6 +1123,48 @@ void dispatch_render(const lr_scene* sc, const SceneK& s, const ViewsK& vk, int6
   else dispatch_dtype_mode<P, 3, LR_COLOR_HUE>(sc, s, vk, nblk, rgba, ns, st);
 }
 
+// Persistent launch: zeroes the counters, then starts `workgroups` resident
+// workgroups (0: as many as the GPU holds at once), rounded up to a multiple
+// of 8.
+template <int P, int NCOMP, typename CT, int MODE, int COLOR>
+hipError_t launch_queue(const SceneK& s, const ViewsK& vk, int64_t nblk, float* rgba, uint32_t* ns, uint32_t* queue,
+                        int queues, int workgroups, hipStream_t st) {
+  const auto kern = render_queue_kernel<P, NCOMP, CT, MODE, COLOR>;
+  int grid = workgroups;
+  if (grid <= 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, 0);
+    if (e != hipSuccess) return e;
+    grid = per_cu * cus;
+  }
+  grid = grid < 8 ? 8 : (grid + 7) / 8 * 8;
+  hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, queue);
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kThreads), 0, st, s, vk, reinterpret_cast<float4*>(rgba), ns,
+                     queue, queues == 8 ? 1 : 0, (uint32_t)nblk);
+  return hipSuccess;
+}
+
+template <int P, int NCOMP, int COLOR>
+hipError_t queue_dtype_mode(const lr_scene* sc, const SceneK& s, const ViewsK& vk, int64_t nblk, float* rgba,
+                            uint32_t* ns, uint32_t* queue, int queues, int workgroups, hipStream_t st) {
+  const bool f16 = sc->bezier_dtype == LR_F16;
+  if (sc->step_mode == LR_STEP_FIXED)
+    return f16 ? launch_queue<P, NCOMP, _Float16, LR_STEP_FIXED, COLOR>(s, vk, nblk, rgba, ns, queue, queues, workgroups, st)
+               : launch_queue<P, NCOMP, float, LR_STEP_FIXED, COLOR>(s, vk, nblk, rgba, ns, queue, queues, workgroups, st);
+  return f16 ? launch_queue<P, NCOMP, _Float16, LR_STEP_ADAPTIVE, COLOR>(s, vk, nblk, rgba, ns, queue, queues, workgroups, st)
+             : launch_queue<P, NCOMP, float, LR_STEP_ADAPTIVE, COLOR>(s, vk, nblk, rgba, ns, queue, queues, workgroups, st);
+}
+
+template <int P>
+hipError_t dispatch_queue(const lr_scene* sc, const SceneK& s, const ViewsK& vk, int64_t nblk, float* rgba,
+                          uint32_t* ns, uint32_t* queue, int queues, int workgroups, hipStream_t st) {
+  if (sc->ncomp == 1)
+    return queue_dtype_mode<P, 1, LR_COLOR_LUT>(sc, s, vk, nblk, rgba, ns, queue, queues, workgroups, st);
+  return queue_dtype_mode<P, 3, LR_COLOR_HUE>(sc, s, vk, nblk, rgba, ns, queue, queues, workgroups, st);
+}
+
 template <int P, int NCOMP, typename CT, int MODE, int COLOR>
 void launch_trace(const SceneK& s, const lr_view& v, const int32_t* pix, int64_t n, int32_t m, float* t, int32_t* e,
                   float* ds, int32_t* cnt, hipStream_t st) {
@@ -1150,15 +1240,29 @@ static void schedule(const lr_scene* sc, const SceneK& s, ViewsK& vk, void* ws, 
   vk.order = order;
 }
 
-// lr_render and lr_render_scheduled: ws null deals the blocks in ring order.
+// How a launch's blocks reach the GPU: in ring order or longest first
+// (cost_order, the order in the workspace), through the hardware's dispatch
+// (queues 0) or persistent workgroups taking them from 1 or 8 counters (the
+// first 256 bytes of the workspace, free once the order is made).
+struct Dispatch {
+  bool cost_order = false;
+  int queues = 0;
+  int workgroups = 0;
+};
+
+// lr_render, lr_render_scheduled and lr_render_persistent; ws is needed
+// when d orders the blocks or queues them.
 static lr_status render_views(const char* who, const lr_scene* sc, const lr_view* views, int32_t n_views,
-                              float* rgba, uint32_t* nsamples, void* ws, int64_t ws_bytes, void* stream) {
+                              float* rgba, uint32_t* nsamples, void* ws, int64_t ws_bytes, Dispatch d, void* stream) {
   SceneK s;
   lr_status st = make_scene(sc, s);
   if (st != LR_OK) return st;
   if (!views || n_views < 1 || !rgba) return fail(LR_EINVAL, "%s: need views, n_views >= 1 and rgba", who);
   for (int i = 0; i < n_views; ++i)
     if ((st = check_view(views[i])) != LR_OK) return st;
+  if (d.queues && (s.lookup != LR_LOOKUP_FOREST || s.shading != LR_SHADE_NONE))
+    return fail(LR_EINVAL, "%s: the persistent form covers the forest look-up without shading", who);
+  if ((d.cost_order || d.queues) && !ws) return fail(LR_EINVAL, "%s: null workspace", who);
   if (ws) {
     const int64_t need = order_workspace(views, n_views);
     if (need < 0) return fail(LR_EINVAL, "%s: image too large for one launch", who);
@@ -1173,13 +1277,23 @@ static lr_status render_views(const char* who, const lr_scene* sc, const lr_view
     ViewsK vk;
     const int64_t nblk = pack_views(views + base, cnt, vk);
     if (nblk <= 0 || nblk > 0x7fffffff) return fail(LR_EINVAL, "%s: image too large for one launch", who);
-    if (ws) schedule(sc, s, vk, ws, hs);
-    switch (sc->p[0]) {
-      case 1: dispatch_render<1>(sc, s, vk, nblk, rgba, nsamples, hs); break;
-      case 2: dispatch_render<2>(sc, s, vk, nblk, rgba, nsamples, hs); break;
-      default: dispatch_render<3>(sc, s, vk, nblk, rgba, nsamples, hs); break;
+    if (d.cost_order) schedule(sc, s, vk, ws, hs);
+    hipError_t err = hipSuccess;
+    if (d.queues) {
+      uint32_t* queue = static_cast<uint32_t*>(ws);
+      switch (sc->p[0]) {
+        case 1: err = dispatch_queue<1>(sc, s, vk, nblk, rgba, nsamples, queue, d.queues, d.workgroups, hs); break;
+        case 2: err = dispatch_queue<2>(sc, s, vk, nblk, rgba, nsamples, queue, d.queues, d.workgroups, hs); break;
+        default: err = dispatch_queue<3>(sc, s, vk, nblk, rgba, nsamples, queue, d.queues, d.workgroups, hs); break;
+      }
+    } else {
+      switch (sc->p[0]) {
+        case 1: dispatch_render<1>(sc, s, vk, nblk, rgba, nsamples, hs); break;
+        case 2: dispatch_render<2>(sc, s, vk, nblk, rgba, nsamples, hs); break;
+        default: dispatch_render<3>(sc, s, vk, nblk, rgba, nsamples, hs); break;
+      }
     }
-    hipError_t err = hipGetLastError();
+    if (err == hipSuccess) err = hipGetLastError();
     if (err != hipSuccess) return fail(LR_EHIP, "%s: %s", who, hipGetErrorString(err));
   }
   return LR_OK;
@@ -1187,7 +1301,7 @@ static lr_status render_views(const char* who, const lr_scene* sc, const lr_view
 
 LR_API lr_status lr_render(const lr_scene* sc, const lr_view* views, int32_t n_views, float* rgba, uint32_t* nsamples,
                            void* stream) {
-  return render_views("lr_render", sc, views, n_views, rgba, nsamples, nullptr, 0, stream);
+  return render_views("lr_render", sc, views, n_views, rgba, nsamples, nullptr, 0, Dispatch{}, stream);
 }
 
 // Dispatch-order scratch of lr_render_scheduled_noalloc: one array per GPU,
@@ -1235,7 +1349,7 @@ LR_API lr_status lr_render_scheduled_noalloc(const lr_scene* sc, const lr_view* 
   const lr_status st = scratch_address(&ws);
   if (st != LR_OK) return st;
   return render_views("lr_render_scheduled_noalloc", sc, views, n_views, rgba, nsamples, ws, kScheduleScratchBytes,
-                      stream);
+                      Dispatch{true, 0, 0}, stream);
 }
 
 LR_API lr_status lr_render_workspace_size(const lr_view* views, int32_t n_views, int64_t* bytes) {
@@ -1253,7 +1367,20 @@ LR_API lr_status lr_render_workspace_size(const lr_view* views, int32_t n_views,
 LR_API lr_status lr_render_scheduled(const lr_scene* sc, const lr_view* views, int32_t n_views, float* rgba,
                                      uint32_t* nsamples, void* workspace, int64_t workspace_bytes, void* stream) {
   if (!workspace) return fail(LR_EINVAL, "lr_render_scheduled: null workspace");
-  return render_views("lr_render_scheduled", sc, views, n_views, rgba, nsamples, workspace, workspace_bytes, stream);
+  return render_views("lr_render_scheduled", sc, views, n_views, rgba, nsamples, workspace, workspace_bytes,
+                      Dispatch{true, 0, 0}, stream);
+}
+
+LR_API lr_status lr_render_persistent(const lr_scene* sc, const lr_view* views, int32_t n_views, float* rgba,
+                                      uint32_t* nsamples, int32_t queues, int32_t cost_order, int32_t workgroups,
+                                      void* workspace, int64_t workspace_bytes, void* stream) {
+  if (queues != 1 && queues != 8) return fail(LR_EINVAL, "lr_render_persistent: queues must be 1 or 8, not %d", queues);
+  if (cost_order != 0 && cost_order != 1)
+    return fail(LR_EINVAL, "lr_render_persistent: cost_order must be 0 or 1, not %d", cost_order);
+  if (workgroups < 0 || workgroups > (1 << 20))
+    return fail(LR_EINVAL, "lr_render_persistent: workgroups %d outside [0, 2^20]", workgroups);
+  return render_views("lr_render_persistent", sc, views, n_views, rgba, nsamples, workspace, workspace_bytes,
+                      Dispatch{cost_order == 1, queues, workgroups}, stream);
 }
 
 LR_API lr_status lr_trace_rays(const lr_scene* sc, const lr_view* view, const int32_t* pix, int64_t n, int32_t max_out,

@@ -465,3 +465,13 @@ def test_render_workspace_size():
     bad.width = 0
     assert size([bad])[0] == L.LR_EINVAL
     assert L.lib().lr_render_workspace_size(None, 1, ctypes.byref(n)) == L.LR_EINVAL
+
+
+def test_render_persistent_argument_checks():
+    """lr_render_persistent refuses queue counts other than 1 and 8, orders
+    other than 0 and 1 and grids outside [0, 2^20] before it reads anything
+    else (host only, no GPU work)."""
+    f = L.lib().lr_render_persistent
+    for queues, order, wg in ((0, 0, 0), (2, 0, 0), (16, 1, 0), (1, 2, 0), (8, -1, 0), (8, 1, -1), (1, 0, (1 << 20) + 1)):
+        assert f(None, None, 1, None, None, queues, order, wg, None, 0, None) == L.LR_EINVAL, (queues, order, wg)
+    assert b"lr_render_persistent" in L.lib().lr_last_error()

@@ -2,7 +2,10 @@
 tiles are dealt changes no pixel, so every render equals lr_render's bit for
 bit, including the per-pixel sample counts, for single and multi-launch view
 sets, both look-up structures, fixed and adaptive steps, FP16 blocks and
-shading; a too-small, null or misaligned workspace is an error."""
+shading; a too-small, null or misaligned workspace is an error.  The
+persistent form (lr_render_persistent: workgroups taking tiles from one or
+eight atomic counters, in either order, with the GPU-filling grid or a small
+one) renders the same bits too."""
 import ctypes
 import dataclasses
 
@@ -88,4 +91,76 @@ def test_workspace_errors():
     base = big[(-big.data_ptr()) % 256:]
     assert lib.lr_render_scheduled(ctypes.byref(s), arr, 1, _ptr(out), None, base.data_ptr() + 4, n, _stream()) == L.LR_EINVAL
     assert lib.lr_render_scheduled(ctypes.byref(s), arr, 1, _ptr(out), None, _ptr(ws), n, _stream()) == L.LR_OK
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("name,blocks,dtype", [("vortex200k", 256, "f32"), ("blobs50k", 128, "f16"),
+                                               ("scalar20k", 64, "f32"), ("scalar_ortho64", 16, "f32")])
+def test_persistent_equals_hardware_dispatch(name, blocks, dtype):
+    import paper_1707_01170_amd as P
+    say("[gpu] persistent dispatch", name, blocks, dtype)
+    wl, sc = scene(name, blocks=blocks, dtype=dtype)
+    total = sum(v.width * v.height for v in wl.views)
+    ref = torch.full((total, 4), -7.0, device="cuda:0")
+    _, _, nref = P.render(sc, wl.views, out=ref, nsamples=True, schedule=False)
+    torch.cuda.synchronize()
+    assert bool((ref != -7.0).all())
+    for queues in (1, 8):
+        for order in (False, True):
+            for wg in (0, 13):
+                out = torch.full((total, 4), -7.0, device="cuda:0")
+                _, _, ns = P.render(sc, wl.views, out=out, nsamples=True, schedule=order, queues=queues,
+                                    workgroups=wg)
+                torch.cuda.synchronize()
+                assert torch.equal(out, ref) and torch.equal(ns, nref), (queues, order, wg)
+    say("%s: %d views, identical in 8 persistent forms" % (name, len(wl.views)))
+
+
+def test_persistent_many_views():
+    """20 views of mixed sizes: two launches reuse the counters in one workspace."""
+    import numpy as np
+
+    import paper_1707_01170_amd as P
+    say("[gpu] persistent dispatch, 20 views")
+    wl, sc = scene("blobs50k", blocks=64, dtype="f32")
+    rng = np.random.default_rng(7)
+    dirs = lrgen.random_directions(rng, 20)
+    sizes = [(40, 28), (96, 96), (200, 64), (17, 33), (128, 200)]
+    views = [lrgen.sphere_view(dirs[k], *sizes[k % len(sizes)]) for k in range(20)]
+    total = sum(v.width * v.height for v in views)
+    ref, _, nref = P.render(sc, views, nsamples=True, schedule=False)
+    for queues, order, wg in ((1, True, 0), (8, False, 8), (8, True, 24)):
+        out = torch.full((total, 4), -7.0, device="cuda:0")
+        _, _, ns = P.render(sc, views, out=out, nsamples=True, schedule=order, queues=queues, workgroups=wg)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref) and torch.equal(ns, nref), (queues, order, wg)
+
+
+def test_persistent_errors():
+    import paper_1707_01170_amd as P
+    from paper_1707_01170_amd import _lib as L
+    from paper_1707_01170_amd.api import _ptr, _stream, view_array
+    say("[gpu] persistent dispatch, errors")
+    wl, sc = scene("blobs50k", blocks=64, dtype="f32")
+    views = [resized(wl.views[0], 64, 48)]
+    ws = P.render_workspace(views, "cuda:0")
+    arr, _ = view_array(views)
+    out = torch.empty((64 * 48, 4), device="cuda:0")
+    lib = L.lib()
+    n = ws.numel()
+
+    def call(s, queues=8, order=1, wg=0, w=ws.data_ptr(), nb=n):
+        return lib.lr_render_persistent(ctypes.byref(s), arr, 1, _ptr(out), None, queues, order, wg, w, nb, _stream())
+
+    s = sc.struct()
+    assert call(s) == L.LR_OK
+    assert call(s, nb=n - 1) == L.LR_ECAPACITY
+    assert call(s, w=None) == L.LR_EINVAL
+    assert call(s, queues=2) == L.LR_EINVAL
+    assert call(s, order=2) == L.LR_EINVAL
+    assert call(s, wg=-1) == L.LR_EINVAL
+    oct_sc = P.Scene(P.Volume(wl.spline, lookup="octree", device="cuda:0"), P.RenderParams.of(wl))
+    assert call(oct_sc.struct()) == L.LR_EINVAL
+    lit = P.Scene(sc.volume, dataclasses.replace(P.RenderParams.of(wl), shading="headlight"))
+    assert call(lit.struct()) == L.LR_EINVAL
     torch.cuda.synchronize()
