@@ -213,6 +213,43 @@ __device__ inline float opacity_of(float alpha, float r) {
   return -(L > -0.125f ? e : big);
 }
 
+// opacity_of, bit for bit, evaluating the logarithm and the exponential only
+// when a lane of the wave needs them (with r = ds / xi small, the series
+// cover most waves).  The illuminated degree-2 vector kernel, short of
+// registers, runs 4 % faster with it (1080p frame 1.36 -> 1.30 ms, FP16
+// blocks 1.31 -> 1.27); the illuminated scalar kernels run 3-11 % slower and
+// the unlit ones as fast or slightly slower, so they keep opacity_of.
+__device__ inline float opacity_of_uniform(float alpha, float r) {
+  float s = 1.0f / 6.0f;
+  s = fmaf(s, alpha, 0.2f);
+  s = fmaf(s, alpha, 0.25f);
+  s = fmaf(s, alpha, 1.0f / 3.0f);
+  s = fmaf(s, alpha, 0.5f);
+  s = fmaf(s, alpha, 1.0f);
+  const float ser = -alpha * s;
+  float ln = ser;
+  if (__ballot(!(alpha < 0.03125f)) != 0) {
+    const float u = 1.0f - alpha;
+    const float d = u - 1.0f;
+    const float lu = __builtin_amdgcn_logf(u) * 0.6931471805599453f * (alpha * __builtin_amdgcn_rcpf(-d));
+    ln = alpha < 0.03125f ? ser : lu;
+  }
+  const float L = ln * r;
+  float e = 1.0f / 5040.0f;
+  e = fmaf(e, L, 1.0f / 720.0f);
+  e = fmaf(e, L, 1.0f / 120.0f);
+  e = fmaf(e, L, 1.0f / 24.0f);
+  e = fmaf(e, L, 1.0f / 6.0f);
+  e = fmaf(e, L, 0.5f);
+  e = fmaf(e, L, 1.0f);
+  e *= L;
+  if (__ballot(!(L > -0.125f)) != 0) {
+    const float big = __builtin_amdgcn_exp2f(L * 1.4426950408889634f) - 1.0f;
+    e = L > -0.125f ? e : big;
+  }
+  return -e;
+}
+
 // ---------------------------------------------------------------- the march
 // Everything a sample produced that a visitor may need.
 template <int P>
@@ -376,15 +413,17 @@ __device__ inline void march(const SceneK& s, const Ray& r, const float4* lut, V
 }
 
 // Alg. 2 with the transmittance carried multiplicatively:
-// a = 1 - (1 - alpha)^(ds/xi), C += T a C_src, T *= 1 - a.
-struct Composite {
+// a = 1 - (1 - alpha)^(ds/xi), C += T a C_src, T *= 1 - a.  UNIFORM picks
+// opacity_of_uniform (the same values).
+template <bool UNIFORM = false>
+struct CompositeT {
   float C[3] = {0.0f, 0.0f, 0.0f};
   float T = 1.0f;
   bool bad = false;          // the look-up met a corrupt reference
   __device__ inline void corrupt(float) { bad = true; }
   __device__ inline void wait() {}
   __device__ inline float opacity(const SceneK& s, float alpha, float ds) const {
-    return opacity_of(alpha, ds * s.inv_xi);
+    return UNIFORM ? opacity_of_uniform(alpha, ds * s.inv_xi) : opacity_of(alpha, ds * s.inv_xi);
   }
   template <int P>
   __device__ inline bool sample(const SceneK& s, const Sample<P>& sm) {
@@ -398,6 +437,7 @@ struct Composite {
   }
   __device__ inline void finish(int) {}
 };
+using Composite = CompositeT<>;
 
 struct TraceVisitor : Composite {
   float* t_out;
@@ -509,7 +549,7 @@ __device__ __forceinline__ void render_block(const SceneK& s, const ViewsK& vk, 
   const lr_view& view = vk.v[v];
   const int64_t o = view.out_offset + (int64_t)py * view.width + px;
   const Ray r = make_ray(view, px, py);
-  struct Counter : Composite {
+  struct Counter : CompositeT<SH != 0 && P == 2 && NCOMP == 3> {
     int n = 0;
     __device__ inline void finish(int k) { n = k; }
   } vis;
