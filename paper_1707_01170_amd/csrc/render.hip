@@ -528,7 +528,8 @@ constexpr int lut_rows() {
 // saved: FP16 blocks
 // are half as many loads (vector frame 0.99 -> 1.16; the serving mix of
 // degree-3 scalar views saturates at 2.19e9 instead of 2.47e9 px/s, a 2048^2
-// view 1.78 -> 2.00 ms), and the illuminated kernels carry the gradient
+// view 1.78 -> 2.00 ms; small degree-3 scalar launches are the exception, see
+// render_gathered_f16_kernel), and the illuminated kernels carry the gradient
 // contraction as well (1.66 -> 1.78).
 template <int P, int NCOMP, typename CT, int SH>
 constexpr int defer_divisor() {
@@ -540,8 +541,9 @@ __device__ __forceinline__ void load_lut(const SceneK& s, float4* lut) {
   __syncthreads();
 }
 
-// Renders the tile of workgroup index b (see locate), one pixel per lane.
-template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK, int SH>
+// Renders the tile of workgroup index b (see locate), one pixel per lane,
+// gathering reloads by DF (see march).
+template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK, int SH, int DF>
 __device__ __forceinline__ void render_block(const SceneK& s, const ViewsK& vk, int64_t b, float4* __restrict__ rgba,
                                              uint32_t* __restrict__ nsamples, float4* lut) {
   int v, px, py;
@@ -553,7 +555,7 @@ __device__ __forceinline__ void render_block(const SceneK& s, const ViewsK& vk, 
     int n = 0;
     __device__ inline void finish(int k) { n = k; }
   } vis;
-  if (r.hit) march<P, NCOMP, CT, MODE, COLOR, LK, SH, defer_divisor<P, NCOMP, CT, SH>()>(s, r, lut, vis);
+  if (r.hit) march<P, NCOMP, CT, MODE, COLOR, LK, SH, DF>(s, r, lut, vis);
   rgba[o] = vis.bad ? make_float4(NAN, NAN, NAN, NAN) : make_float4(vis.C[0], vis.C[1], vis.C[2], 1.0f - vis.T);
   if (nsamples) nsamples[o] = (uint32_t)vis.n;
 }
@@ -563,7 +565,26 @@ __global__ __launch_bounds__(kThreads) void render_kernel(const SceneK s, const 
                                                          uint32_t* __restrict__ nsamples) {
   __shared__ float4 lut[lut_rows<P, NCOMP, CT>()];   // rows beyond 256 are reserved, never touched
   load_lut(s, lut);
-  render_block<P, NCOMP, CT, MODE, COLOR, LK, SH>(s, vk, blockIdx.x, rgba, nsamples, lut);
+  render_block<P, NCOMP, CT, MODE, COLOR, LK, SH, defer_divisor<P, NCOMP, CT, SH>()>(s, vk, blockIdx.x, rgba,
+                                                                                     nsamples, lut);
+}
+
+// Degree-3 scalar fields from FP16 blocks in launches that do not fill the
+// GPU (at most kGatherTiles workgroups): the chain of the longest rays then
+// bounds the launch, and gathering the reloads, as the FP32 kernels do,
+// shortens it (blob views of 512^2-1280^2 0.80-0.84 -> 0.69-0.71 ms), where
+// in fuller launches it costs more than it saves (1448^2 0.85 -> 0.88 ms,
+// 2048^2 1.52 -> 1.69, four 1024^2 views in one launch 2.00 -> 2.05).  The
+// same image bit for bit.  (Degree-2 scalar views gain nothing from it.)
+constexpr int64_t kGatherTiles = 28672;
+
+template <int MODE, int LK>
+__global__ __launch_bounds__(kThreads) void render_gathered_f16_kernel(const SceneK s, const ViewsK vk,
+                                                                      float4* __restrict__ rgba,
+                                                                      uint32_t* __restrict__ nsamples) {
+  __shared__ float4 lut[lut_rows<3, 1, _Float16>()];
+  load_lut(s, lut);
+  render_block<3, 1, _Float16, MODE, LR_COLOR_LUT, LK, 0, 2>(s, vk, blockIdx.x, rgba, nsamples, lut);
 }
 
 // Persistent form of the same launch, kept to compare work queues with the
@@ -601,8 +622,8 @@ void render_queue_kernel(const SceneK s, const ViewsK vk,
     if (threadIdx.x == 0) item = atomicAdd(&queue[8 * x], 1u);
     item = __shfl(item, 0);
     if (item >= items) break;
-    render_block<P, NCOMP, CT, MODE, COLOR, LR_LOOKUP_FOREST, 0>(s, vk, (int64_t)item * stride + x, rgba, nsamples,
-                                                                 lut);
+    render_block<P, NCOMP, CT, MODE, COLOR, LR_LOOKUP_FOREST, 0, defer_divisor<P, NCOMP, CT, 0>()>(
+        s, vk, (int64_t)item * stride + x, rgba, nsamples, lut);
   }
 }
 
@@ -624,7 +645,7 @@ void render_lit_vector2_kernel(const SceneK s, const ViewsK vk, float4* __restri
                                uint32_t* __restrict__ nsamples) {
   __shared__ float4 lut[256];
   load_lut(s, lut);
-  render_block<2, 3, CS, MODE, LR_COLOR_HUE, LR_LOOKUP_FOREST, 1>(s, vk, blockIdx.x, rgba, nsamples, lut);
+  render_block<2, 3, CS, MODE, LR_COLOR_HUE, LR_LOOKUP_FOREST, 1, 0>(s, vk, blockIdx.x, rgba, nsamples, lut);
 }
 
 template <int P, int NCOMP, typename CT, int MODE, int COLOR, int LK, int SH>
@@ -1135,7 +1156,20 @@ void launch_render(const SceneK& s, const ViewsK& vk, int64_t nblk, float* rgba,
     else
       hipLaunchKernelGGL((render_kernel<P, NCOMP, CT, MODE, COLOR, LR_LOOKUP_FOREST, 1>), dim3((unsigned)nblk),
                          dim3(kThreads), 0, st, s, vk, out, ns);
-  } else if (s.lookup == LR_LOOKUP_OCTREE)
+    return;
+  }
+  if constexpr (P == 3 && NCOMP == 1 && std::is_same<CT, _Float16>::value) {
+    if (nblk <= kGatherTiles) {
+      if (s.lookup == LR_LOOKUP_OCTREE)
+        hipLaunchKernelGGL((render_gathered_f16_kernel<MODE, LR_LOOKUP_OCTREE>), dim3((unsigned)nblk), dim3(kThreads),
+                           0, st, s, vk, out, ns);
+      else
+        hipLaunchKernelGGL((render_gathered_f16_kernel<MODE, LR_LOOKUP_FOREST>), dim3((unsigned)nblk), dim3(kThreads),
+                           0, st, s, vk, out, ns);
+      return;
+    }
+  }
+  if (s.lookup == LR_LOOKUP_OCTREE)
     hipLaunchKernelGGL((render_kernel<P, NCOMP, CT, MODE, COLOR, LR_LOOKUP_OCTREE, 0>), dim3((unsigned)nblk),
                        dim3(kThreads), 0, st, s, vk, out, ns);
   else

@@ -131,8 +131,9 @@ def test_fp16_blocks_equal_fp32_kernel_on_widened_blocks(name, shading):
 def test_gathered_reloads_leave_the_full_frame_unchanged(name, blocks):
     """The benchmark's frame (vortex200k at 1920x1080 through the 256^3
     forest) and the serving volume's view, rendered by the FP32 kernel, which
-    gathers block reloads, and by the FP16 kernel, which reloads at once, from
-    the same block values: identical bit for bit."""
+    gathers block reloads, and by the FP16 kernel (which reloads at once for
+    the vector frame and, for the one blob view, gathers as well), from the
+    same block values: identical bit for bit."""
     import paper_1707_01170_amd as P
     say("[gpu] gathered reloads, full frame", name, blocks)
     wl, sc16 = scene(name, blocks=blocks, dtype="f16")
@@ -145,6 +146,27 @@ def test_gathered_reloads_leave_the_full_frame_unchanged(name, blocks):
     torch.cuda.synchronize()
     say("%s %dx%d: %d samples" % (name, view.width, view.height, int(nb.sum())))
     assert torch.equal(na, nb) and torch.equal(a, b)
+
+
+@pytest.mark.parametrize("lookup", ["forest", "octree"])
+def test_small_fp16_degree3_launch_equals_large(lookup):
+    """Degree-3 scalar FP16 launches of at most 28 672 workgroups gather
+    block reloads (one 1024^2 view: 16 384); a launch of four copies of the
+    view (65 536) reloads at once: every copy equals the single view bit for
+    bit, sample counts included."""
+    import paper_1707_01170_amd as P
+    say("[gpu] small and large FP16 degree-3 launches", lookup)
+    wl = workload("blobs50k")
+    vol = P.Volume(wl.spline, blocks=128, dtype="f16", lookup=lookup)
+    sc = P.Scene(vol, P.RenderParams.of(wl))
+    view = wl.views[0]
+    assert (view.width, view.height) == (1024, 1024)
+    a, _, na = P.render(sc, [view], nsamples=True, schedule=False)
+    b, _, nb = P.render(sc, [view] * 4, nsamples=True, schedule=False)
+    torch.cuda.synchronize()
+    n = view.width * view.height
+    for k in range(4):
+        assert torch.equal(b[k * n:(k + 1) * n], a) and torch.equal(nb[k * n:(k + 1) * n], na), k
 
 
 @pytest.mark.parametrize("name", ["blobs50k", "scalar20k"])
