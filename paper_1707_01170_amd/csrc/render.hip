@@ -607,11 +607,8 @@ constexpr int queue_waves() {
 
 template <int P, int NCOMP, typename CT, int MODE, int COLOR>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(queue_waves<P, NCOMP, CT>())))
-void render_queue_kernel(const SceneK s, const ViewsK vk,
-                                                               float4* __restrict__ rgba,
-                                                               uint32_t* __restrict__ nsamples,
-                                                               uint32_t* __restrict__ queue, int per_xcd,
-                                                               uint32_t nblk) {
+void render_queue_kernel(const SceneK s, const ViewsK vk, float4* __restrict__ rgba, uint32_t* __restrict__ nsamples,
+                         uint32_t* __restrict__ queue, int per_xcd, uint32_t nblk) {
   __shared__ float4 lut[lut_rows<P, NCOMP, CT>()];
   load_lut(s, lut);
   const uint32_t x = per_xcd ? blockIdx.x & 7u : 0u;
