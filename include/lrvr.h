@@ -308,10 +308,11 @@ lr_status lr_render(const lr_scene* sc, const lr_view* views, int32_t n_views, f
 
 /* lr_render with a dispatch order estimated per launch: the same images, bit
  * for bit, and the same errors, in less time when the work per pixel is
- * uneven.  A launch's blocks of 16x16 pixels are dealt to the GPU longest
- * first; a block's cost is estimated from the element sizes (Eq. 4 steps) at
- * 32 points along its centre ray, and lr_render instead deals the blocks from
- * the middle of each view outwards.
+ * uneven.  A block of 16x16 pixels is estimated from the element sizes (Eq. 4
+ * steps) at 32 points along its centre ray; groups of 2x2 blocks are dealt to
+ * the GPU's eight XCDs longest first (each group whole to one XCD, whose
+ * cache its rays share).  lr_render instead deals the blocks from the middle
+ * of each view outwards.
  * workspace        device memory, 256-byte aligned, of at least the bytes
  *                  lr_render_workspace_size returns for the same views; the
  *                  caller owns it; it is read and written on stream only, so
@@ -324,18 +325,21 @@ lr_status lr_render_scheduled(const lr_scene* sc, const lr_view* views, int32_t 
 
 /* lr_render_scheduled for callers that cannot allocate device memory (code
  * under graph capture, tight serving loops, harnesses that forbid it): the
- * workspace is a 2 MiB array the library holds on each GPU it runs on, until
- * the process ends, so no call allocates.  At most 262 144 blocks of 16x16
- * pixels per launch of up to 16 views (16 views of 2048^2); larger requests
- * return LR_ECAPACITY and render nothing.  Calls that overlap on one GPU
- * share the array and race: serialise them (one stream, or events). */
+ * workspace is a 2 MiB + 64 KiB array the library holds on each GPU it runs
+ * on, until the process ends, so no call allocates.  It holds the workspace of a launch
+ * of up to 16 views with about 262 144 blocks of 16x16 pixels (16 views of
+ * 2048^2 fit exactly); larger requests return LR_ECAPACITY and render
+ * nothing.  Calls that overlap on one GPU share the array and race:
+ * serialise them (one stream, or events). */
 lr_status lr_render_scheduled_noalloc(const lr_scene* sc, const lr_view* views, int32_t n_views,
                                       float* rgba, uint32_t* nsamples, void* stream);
 
 /* Bytes of workspace lr_render_scheduled needs for these views (host only,
- * no GPU work): 8 bytes per 16x16-pixel block of the largest launch (16
- * views per launch), each half rounded up to 256.  LR_EINVAL for null
- * arguments or invalid views. */
+ * no GPU work), for the largest launch (16 views per launch): 4 bytes per
+ * 16x16-pixel block for the estimates, then, with s slots of the dealing
+ * order (per view, 32 for every 8 groups of 2x2 blocks, rounded up), s / 4
+ * bytes for the groups' XCDs and 4 s bytes for the order, each part rounded
+ * up to 256.  LR_EINVAL for null arguments or invalid views. */
 lr_status lr_render_workspace_size(const lr_view* views, int32_t n_views, int64_t* bytes);
 
 /* lr_render through persistent workgroups that take the launch's 8x8-pixel

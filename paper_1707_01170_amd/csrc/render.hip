@@ -58,7 +58,8 @@ struct ViewsK {
   int64_t quad_base[kMaxViews + 1];    // prefix sums of kQuad x kQuad blocks of tiles
   int32_t quads_x[kMaxViews];
   int32_t n;
-  const int32_t* order;                // per view, its blocks by decreasing estimated cost; null: ring order
+  const int32_t* order;                // the dealing order (see locate); null: ring order
+  int64_t slot_base[kMaxViews + 1];    // prefix sums of the order's slots per view (see quad_order_kernel)
 };
 
 struct Ray {
@@ -482,23 +483,29 @@ struct TraceVisitor : Composite {
 // 1.51, images unchanged; dealt row by row, a one-view launch took 20 %
 // longer per view than a launch of four copies of it).  b -> (block, tile)
 // is a bijection onto the blocks padded to a multiple of 8; tiles outside
-// the image do nothing.
+// the image do nothing.  With a dealing order (quad_order_kernel), q indexes
+// its slots instead: slot q holds a block of the view, or -1 (nothing).
 __device__ inline bool locate(const ViewsK& vk, int64_t b, int& v, int& px, int& py) {
   constexpr int QQ = kQuad * kQuad;
   const int64_t k = b >> 3;
   const int64_t q = (b & 7) + 8 * (k / QQ);
   const int w = (int)(k % QQ);
   v = 0;
-  if (q >= vk.quad_base[vk.n]) return false;
-  while (v + 1 < vk.n && q >= vk.quad_base[v + 1]) ++v;
-  const int64_t lq = q - vk.quad_base[v];
-  const int qw = vk.quads_x[v], qh = (int)((vk.quad_base[v + 1] - vk.quad_base[v]) / qw);
-  int qx, qy;
+  int qx, qy, qw;
   if (vk.order) {
-    const int32_t o = vk.order[vk.quad_base[v] + lq];
+    if (q >= vk.slot_base[vk.n]) return false;
+    while (v + 1 < vk.n && q >= vk.slot_base[v + 1]) ++v;
+    const int32_t o = vk.order[q];
+    if (o < 0) return false;
+    qw = vk.quads_x[v];
     qx = o % qw;
     qy = o / qw;
   } else {
+    if (q >= vk.quad_base[vk.n]) return false;
+    while (v + 1 < vk.n && q >= vk.quad_base[v + 1]) ++v;
+    const int64_t lq = q - vk.quad_base[v];
+    qw = vk.quads_x[v];
+    const int qh = (int)((vk.quad_base[v + 1] - vk.quad_base[v]) / qw);
     ring_cell(lq, qw, qh, qx, qy);
   }
   const int gx = qx * kQuad + w % kQuad;
@@ -694,11 +701,12 @@ __global__ void lookup_octree_kernel(const uint32_t* __restrict__ root, const ui
 // a block's cost is estimated before the render: half a wavefront per block of
 // tiles, 32 points evenly spaced along the block's centre ray, each adding
 // its stretch of the ray divided by the smallest side of the element there.
-// The blocks of each view are then ranked by decreasing estimate (a counting
-// sort on 64 levels, one workgroup per view) and the render deals them in
-// that order: the longest rays start first, whatever the shape of the dense
-// region in the image.  The order changes no pixel; blocks of one level are
-// ordered arbitrarily.
+// quad_order_kernel then deals the blocks: groups of 2 x 2 neighbouring
+// blocks (32 x 32 pixels, whose rays share elements) go whole to one XCD and
+// its L2, ranked by their summed estimates and dealt in snake order (0..7,
+// 7..0, ...), so the XCDs get the same number of groups of similar total
+// cost; each XCD then takes its blocks longest first.  The order changes no
+// pixel; blocks of one level are ordered arbitrarily.
 template <int LK>
 __global__ __launch_bounds__(64) void quad_cost_kernel(const SceneK s, const ViewsK vk, int fixed,
                                                        float* __restrict__ cost) {
@@ -739,41 +747,102 @@ __global__ __launch_bounds__(64) void quad_cost_kernel(const SceneK s, const Vie
 
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderLevels = 64;
+// Blocks per side of a dealing group.  On the 1080p vector frame: L2-to-
+// fabric reads 902 MB per frame when single blocks were dealt to the XCDs by
+// rank, 506 MB with 2 x 2 groups (0.784 -> 0.778 ms), 323 MB with 4 x 4
+// groups (0.790 ms, small views 1-2 % slower: coarser groups balance worse).
+constexpr int kGS = 2;
 
+// One workgroup per view, in two passes over counting sorts on 64 levels.
+// First the kGS x kGS groups of blocks are ranked by their summed estimates and
+// dealt to the XCDs in snake order, rank r to XCD x(r) (0..7, 7..0, ...),
+// recorded in xmap (one entry per group).  Then each XCD's blocks are ranked
+// by their own estimates, and block rank k of XCD x goes to slot x + 8 k of
+// the view (from vk.slot_base[v]), the index locate gives to the k-th
+// block-worth of workgroups the hardware deals to XCD x.  An XCD holds at
+// most kGS^2 ceil(groups / 8) blocks, so the slots, 8 kGS^2 ceil(groups / 8)
+// per view, suffice; those without a block hold -1.
 __global__ __launch_bounds__(kOrderThreads) void quad_order_kernel(const ViewsK vk, const float* __restrict__ cost,
+                                                                   int8_t* __restrict__ xmap,
                                                                    int32_t* __restrict__ order) {
   __shared__ float wmax[kOrderThreads / 64];
-  __shared__ int32_t first[kOrderLevels];
+  __shared__ int32_t first[8][kOrderLevels];
   const int v = blockIdx.x, tid = threadIdx.x;
   const int64_t base = vk.quad_base[v];
-  const int n = (int)(vk.quad_base[v + 1] - base);
-  float m = 0.0f;
-  for (int i = tid; i < n; i += kOrderThreads) m = fmaxf(m, cost[base + i]);
-  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
-  if ((tid & 63) == 0) wmax[tid >> 6] = m;
-  if (tid < kOrderLevels) first[tid] = 0;
-  __syncthreads();
-  float mx = 0.0f;
-  for (int w = 0; w < kOrderThreads / 64; ++w) mx = fmaxf(mx, wmax[w]);
-  const float scale = mx > 0.0f ? (float)(kOrderLevels - 1) / mx : 0.0f;
-  auto level = [&](float c) {   // 0 for the costliest blocks
+  const int qw = vk.quads_x[v];
+  const int nq = (int)(vk.quad_base[v + 1] - base);
+  const int qh = nq / qw;
+  const int gw = (qw + kGS - 1) / kGS, gh = (qh + kGS - 1) / kGS, ng = gw * gh;
+  int32_t* const slots = order + vk.slot_base[v];
+  int8_t* const xm = xmap + vk.slot_base[v] / (kGS * kGS);   // 8 ceil(ng / 8) >= ng entries per view
+  const int nslots = (int)(vk.slot_base[v + 1] - vk.slot_base[v]);
+  auto group_cost = [&](int g) {   // the same sum, in the same order, every time
+    const int gx = g % gw, gy = g / gw;
+    float c = 0.0f;
+    for (int j = 0; j < kGS * kGS; ++j) {
+      const int qx = kGS * gx + j % kGS, qy = kGS * gy + j / kGS;
+      if (qx < qw && qy < qh) c += cost[base + (int64_t)qy * qw + qx];
+    }
+    return c;
+  };
+  auto block_max = [&](float m) {   // the workgroup's maximum of m
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if ((tid & 63) == 0) wmax[tid >> 6] = m;
+    __syncthreads();
+    float mx = 0.0f;
+    for (int w = 0; w < kOrderThreads / 64; ++w) mx = fmaxf(mx, wmax[w]);
+    __syncthreads();
+    return mx;
+  };
+  auto level_of = [](float c, float scale) {   // 0 for the costliest
     int l = (int)(c * scale);
     l = l < 0 ? 0 : (l > kOrderLevels - 1 ? kOrderLevels - 1 : l);
     return kOrderLevels - 1 - l;
   };
-  for (int i = tid; i < n; i += kOrderThreads) atomicAdd(&first[level(cost[base + i])], 1);
-  __syncthreads();
-  if (tid < kOrderLevels) {   // one wavefront: exclusive scan of the level counts
-    const int own = first[tid];
-    int x = own;
-    for (int off = 1; off < kOrderLevels; off <<= 1) {
-      const int y = __shfl_up(x, off);
-      if (tid >= off) x += y;
+  auto scan = [&](int rows) {   // exclusive scans of first[0..rows-1][], one wavefront per row
+    const int w = tid >> 6, l = tid & 63;
+    if (w < rows) {
+      const int own = first[w][l];
+      int x = own;
+      for (int off = 1; off < kOrderLevels; off <<= 1) {
+        const int y = __shfl_up(x, off);
+        if (l >= off) x += y;
+      }
+      first[w][l] = x - own;
     }
-    first[tid] = x - own;
-  }
+    __syncthreads();
+  };
+  for (int i = tid; i < nslots; i += kOrderThreads) slots[i] = -1;
+  if (tid < 8 * kOrderLevels) first[tid / kOrderLevels][tid % kOrderLevels] = 0;
+  // groups -> XCDs
+  float m = 0.0f;
+  for (int g = tid; g < ng; g += kOrderThreads) m = fmaxf(m, group_cost(g));
+  const float mg = block_max(m);
+  const float gscale = mg > 0.0f ? (float)(kOrderLevels - 1) / mg : 0.0f;
+  for (int g = tid; g < ng; g += kOrderThreads) atomicAdd(&first[0][level_of(group_cost(g), gscale)], 1);
   __syncthreads();
-  for (int i = tid; i < n; i += kOrderThreads) order[base + atomicAdd(&first[level(cost[base + i])], 1)] = i;
+  scan(1);
+  for (int g = tid; g < ng; g += kOrderThreads) {
+    const int r = atomicAdd(&first[0][level_of(group_cost(g), gscale)], 1);
+    const int round = r >> 3, pos = r & 7;
+    xm[g] = (int8_t)((round & 1) ? 7 - pos : pos);
+  }
+  __syncthreads();   // xm visible to the workgroup; the -1 fill ordered before the writes below
+  if (tid < kOrderLevels) first[0][tid] = 0;
+  // each XCD's blocks by their own estimates
+  m = 0.0f;
+  for (int i = tid; i < nq; i += kOrderThreads) m = fmaxf(m, cost[base + i]);
+  const float mb = block_max(m);
+  const float bscale = mb > 0.0f ? (float)(kOrderLevels - 1) / mb : 0.0f;
+  auto xcd_of = [&](int i) { return (int)xm[((i / qw) / kGS) * gw + (i % qw) / kGS]; };
+  for (int i = tid; i < nq; i += kOrderThreads) atomicAdd(&first[xcd_of(i)][level_of(cost[base + i], bscale)], 1);
+  __syncthreads();
+  scan(8);
+  for (int i = tid; i < nq; i += kOrderThreads) {
+    const int x = xcd_of(i);
+    const int k = atomicAdd(&first[x][level_of(cost[base + i], bscale)], 1);
+    slots[x + 8 * k] = i;
+  }
 }
 
 // ---------------------------------------------------------------- adjoint
@@ -1137,10 +1206,16 @@ int64_t pack_views(const lr_view* views, int32_t n, ViewsK& vk) {
     vk.v[i] = views[i];
     const int64_t gx = (views[i].width + kGroup - 1) / kGroup, gy = (views[i].height + kGroup - 1) / kGroup;
     vk.quads_x[i] = (int32_t)((gx + kQuad - 1) / kQuad);
-    vk.quad_base[i + 1] = vk.quad_base[i] + (int64_t)vk.quads_x[i] * ((gy + kQuad - 1) / kQuad);
+    const int64_t qh = (gy + kQuad - 1) / kQuad;
+    vk.quad_base[i + 1] = vk.quad_base[i] + (int64_t)vk.quads_x[i] * qh;
+    const int64_t groups = ((vk.quads_x[i] + kGS - 1) / kGS) * ((qh + kGS - 1) / kGS);   // kGS x kGS blocks each
+    vk.slot_base[i + 1] = vk.slot_base[i] + 8 * kGS * kGS * ((groups + 7) / 8);
   }
-  return 8 * ((vk.quad_base[n] + 7) / 8) * (int64_t)kQuad * kQuad;   // workgroups to launch
+  return 8 * ((vk.quad_base[n] + 7) / 8) * (int64_t)kQuad * kQuad;   // workgroups to launch in ring order
 }
+
+// Workgroups of a launch dealt by its dealing order: one per tile slot.
+int64_t ordered_workgroups(const ViewsK& vk) { return vk.slot_base[vk.n] * kQuad * kQuad; }
 
 template <int P, int NCOMP, typename CT, int MODE, int COLOR>
 void launch_render(const SceneK& s, const ViewsK& vk, int64_t nblk, float* rgba, uint32_t* ns, hipStream_t st) {
@@ -1275,9 +1350,15 @@ void dispatch_trace(const lr_scene* sc, const SceneK& s, const lr_view& v, const
 
 using lrvr::fail;
 
-// Bytes of the dispatch-order workspace for one launch of nq blocks: the
-// estimates, then the order, each 256-byte aligned.
-static int64_t order_bytes(int64_t nq) { return 2 * ((nq * 4 + 255) / 256 * 256); }
+// Bytes of the dispatch-order workspace for one launch: the blocks' estimates
+// (4 bytes each), the groups' XCDs (1 byte per 4 slots) and the order (4
+// bytes per slot), each 256-byte aligned.
+static int64_t round256(int64_t b) { return (b + 255) / 256 * 256; }
+static int64_t cost_bytes(const ViewsK& vk) { return round256(vk.quad_base[vk.n] * 4); }
+static int64_t xmap_bytes(const ViewsK& vk) { return round256(vk.slot_base[vk.n] / (kGS * kGS)); }
+static int64_t order_bytes(const ViewsK& vk) {
+  return cost_bytes(vk) + xmap_bytes(vk) + round256(vk.slot_base[vk.n] * 4);
+}
 
 // Largest workspace any launch of these views needs (views in launches of
 // kMaxViews); -1 if a launch would be too large.
@@ -1287,19 +1368,20 @@ static int64_t order_workspace(const lr_view* views, int32_t n_views) {
     const int cnt = n_views - base < kMaxViews ? n_views - base : kMaxViews;
     ViewsK vk;
     const int64_t nblk = pack_views(views + base, cnt, vk);
-    if (nblk <= 0 || nblk > 0x7fffffff) return -1;
-    const int64_t b = order_bytes(vk.quad_base[cnt]);
+    if (nblk <= 0 || nblk > 0x7fffffff || ordered_workgroups(vk) > 0x7fffffff) return -1;
+    const int64_t b = order_bytes(vk);
     need = b > need ? b : need;
   }
   return need;
 }
 
-// Estimates the blocks' costs and ranks them into ws (order_bytes of the
-// launch's blocks), and points vk at the order.
+// Estimates the blocks' costs and deals them into ws (order_bytes of the
+// launch), and points vk at the order.
 static void schedule(const lr_scene* sc, const SceneK& s, ViewsK& vk, void* ws, hipStream_t st) {
   const int64_t nq = vk.quad_base[vk.n];
   float* cost = static_cast<float*>(ws);
-  int32_t* order = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + order_bytes(nq) / 2);
+  int8_t* xmap = reinterpret_cast<int8_t*>(static_cast<char*>(ws) + cost_bytes(vk));
+  int32_t* order = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + cost_bytes(vk) + xmap_bytes(vk));
   const int fixed = sc->step_mode == LR_STEP_FIXED;
   if (s.lookup == LR_LOOKUP_OCTREE)
     hipLaunchKernelGGL(quad_cost_kernel<LR_LOOKUP_OCTREE>, dim3((unsigned)((nq + 1) / 2)), dim3(64), 0, st, s, vk,
@@ -1307,7 +1389,7 @@ static void schedule(const lr_scene* sc, const SceneK& s, ViewsK& vk, void* ws, 
   else
     hipLaunchKernelGGL(quad_cost_kernel<LR_LOOKUP_FOREST>, dim3((unsigned)((nq + 1) / 2)), dim3(64), 0, st, s, vk,
                        fixed, cost);
-  hipLaunchKernelGGL(quad_order_kernel, dim3((unsigned)vk.n), dim3(kOrderThreads), 0, st, vk, cost, order);
+  hipLaunchKernelGGL(quad_order_kernel, dim3((unsigned)vk.n), dim3(kOrderThreads), 0, st, vk, cost, xmap, order);
   vk.order = order;
 }
 
@@ -1346,7 +1428,8 @@ static lr_status render_views(const char* who, const lr_scene* sc, const lr_view
   for (int base = 0; base < n_views; base += kMaxViews) {
     const int cnt = n_views - base < kMaxViews ? n_views - base : kMaxViews;
     ViewsK vk;
-    const int64_t nblk = pack_views(views + base, cnt, vk);
+    int64_t nblk = pack_views(views + base, cnt, vk);
+    if (d.cost_order) nblk = ordered_workgroups(vk);
     if (nblk <= 0 || nblk > 0x7fffffff) return fail(LR_EINVAL, "%s: image too large for one launch", who);
     if (d.cost_order) schedule(sc, s, vk, ws, hs);
     hipError_t err = hipSuccess;
@@ -1380,7 +1463,7 @@ LR_API lr_status lr_render(const lr_scene* sc, const lr_view* views, int32_t n_v
 // uses only the device address hipGetSymbolAddress gives for it (per device,
 // on that device's first call); the array's name is no device address on the
 // host.  Calls that overlap on one GPU share the array and race.
-constexpr int64_t kScheduleScratchBytes = (int64_t)2 << 20;   // 262 144 blocks of 16x16 pixels per launch
+constexpr int64_t kScheduleScratchBytes = ((int64_t)2 << 20) + (64 << 10);   // 16 views of 2048^2 per launch
 static __device__ __align__(256) unsigned char scratch[kScheduleScratchBytes];
 static std::mutex g_scratch_mutex;
 static void* g_scratch[256];   // per device id
@@ -1414,7 +1497,7 @@ LR_API lr_status lr_render_scheduled_noalloc(const lr_scene* sc, const lr_view* 
   if (need > kScheduleScratchBytes)
     return fail(LR_ECAPACITY,
                 "lr_render_scheduled_noalloc: a launch of these views needs %lld bytes of dispatch-order scratch; "
-                "the library holds %lld (262 144 blocks of 16x16 pixels per launch of up to 16 views)",
+                "the library holds %lld (16 views of 2048^2 per launch)",
                 (long long)need, (long long)kScheduleScratchBytes);
   void* ws = nullptr;
   const lr_status st = scratch_address(&ws);

@@ -437,9 +437,11 @@ def test_header_is_plain_c(tmp_path):
 
 
 def test_render_workspace_size():
-    """Host-only query of lr_render_scheduled's workspace: 8 bytes per
-    16x16-pixel block of the largest launch (16 views per launch), each half
-    rounded up to 256 bytes; bad views are errors."""
+    """Host-only query of lr_render_scheduled's workspace, for the largest
+    launch (16 views per launch): 4 bytes per 16x16-pixel block, then for s
+    dealing slots (32 per 8 groups of 2x2 blocks of a view, rounded up) s / 4
+    bytes of group XCDs and 4 s bytes of order, each part rounded up to 256
+    bytes; bad views are errors."""
     from paper_1707_01170_amd.api import view_array
     n = ctypes.c_int64(0)
 
@@ -449,14 +451,19 @@ def test_render_workspace_size():
         return st, n.value
 
     def expect(views):
+        r256 = lambda b: (b + 255) // 256 * 256
         per_launch = []
         for k in range(0, len(views), 16):
-            q = sum(((v.width + 15) // 16) * ((v.height + 15) // 16) for v in views[k:k + 16])
-            per_launch.append(2 * ((q * 4 + 255) // 256 * 256))
+            q = slots = 0
+            for v in views[k:k + 16]:
+                qw, qh = (v.width + 15) // 16, (v.height + 15) // 16
+                q += qw * qh
+                slots += 32 * ((((qw + 1) // 2) * ((qh + 1) // 2) + 7) // 8)
+            per_launch.append(r256(4 * q) + r256(slots // 4) + r256(4 * slots))
         return max(per_launch)
 
     v = lrgen.sphere_view(np.array([1.0, 0.2, 0.3]), 1920, 1080)
-    assert size([v]) == (L.LR_OK, 65536) == (L.LR_OK, expect([v]))
+    assert size([v]) == (L.LR_OK, 32768 + 2048 + 32768) == (L.LR_OK, expect([v]))
     rng = np.random.default_rng(2)
     views = [lrgen.sphere_view(lrgen.random_directions(rng, 1)[0], int(w), int(h))
              for w, h in rng.integers(1, 700, size=(21, 2))]

@@ -140,13 +140,11 @@ def test_embedded_error_matches_oracle(method):
     e_gpu = ost.error_metric(ref, pts[:, :, :3].astype(np.float64), tim, cnt)
     e_orc = ost.error_metric(ref, X, T, c)
     say("embedded %s: E gpu %.3e oracle %.3e, points gpu %d oracle %d" % (method, e_gpu, e_orc, cnt.sum(), c.sum()))
-    # lines with the same number of accepted steps, point by point: the
-    # accept/reject decisions and step factors come from error estimates of
-    # FP32 field values (GPU) and FP64 ones (oracle)
-    # The step factors come from error estimates of FP32 (GPU) and FP64
-    # (oracle) field values, so the accepted times drift apart slightly; a
-    # point then differs from the oracle's by the distance travelled in that
-    # time difference (speed |f| times |dt|) plus the FP32 evaluation.
+    # Lines with the same number of accepted steps, point by point.  The step
+    # factors come from error estimates of FP32 (GPU) and FP64 (oracle) field
+    # values, so the accepted times drift apart slightly; a point then differs
+    # from the oracle's by the distance travelled in that time difference
+    # (speed |f| times |dt|) plus the FP32 evaluation.
     equal = np.nonzero(cnt == c)[0]
     dx = dt = excess = 0.0
     for j in equal:
