@@ -968,9 +968,6 @@ struct Adjoint : Composite {
 
   // Adds the sums of the element the lane leaves (cur) into the table.  Every
   // active lane calls it (with cur < 0 if it has nothing to add), so that a
-  // full table can be spilled by the whole wave.
-  // Adds the sums of the element the lane leaves (cur) into the table.  Every
-  // active lane calls it (with cur < 0 if it has nothing to add), so that a
   // full table can be spilled by the whole wave.  A lane that waited for a
   // gathered reload step was inactive in any spill meanwhile, so its entry
   // claim may be stale: it claims again.
