@@ -72,6 +72,70 @@ def test_scheduled_octree_and_many_views():
     assert torch.equal(a, b) and torch.equal(na, nb)
 
 
+def _r256(b):
+    return (b + 255) // 256 * 256
+
+
+@pytest.mark.parametrize("name", ["vortex200k", "blobs50k"])
+def test_dealing_order_in_workspace(name):
+    """The dealing order the scheduled render leaves in its workspace, read
+    back and checked against its definition: per view, every 16x16-pixel
+    block in exactly one slot (the others -1); slot s on XCD s mod 8 (the
+    hardware deals workgroups round-robin to the XCDs); the four blocks of a
+    2x2 group on the XCD its group was dealt to (the XCD map); groups dealt
+    evenly (counts per XCD differ by at most one); and each XCD's blocks in
+    slots x, x + 8, ... by non-increasing estimate on the 64 levels of the
+    view's largest estimate, without gaps.  Layout of the workspace: FP32
+    estimates per block, one XCD byte per group, then int32 slots, each part
+    256-byte aligned."""
+    import numpy as np
+    import paper_1707_01170_amd as P
+    say("[gpu] dealing order in the workspace", name)
+    wl, sc = scene(name, blocks=256 if name == "vortex200k" else 128)
+    rng = np.random.default_rng(11)
+    dirs = lrgen.random_directions(rng, 3)
+    views = [wl.views[0], lrgen.sphere_view(dirs[0], 200, 120), lrgen.sphere_view(dirs[1], 33, 47),
+             lrgen.sphere_view(dirs[2], 512, 512)]
+    ws = P.render_workspace(views, "cuda:0")
+    P.render(sc, views, workspace=ws)
+    torch.cuda.synchronize()
+    raw = ws.cpu().numpy()
+    qdims = [((v.width + 15) // 16, (v.height + 15) // 16) for v in views]
+    groups = [((qw + 1) // 2) * ((qh + 1) // 2) for qw, qh in qdims]
+    nslots = [32 * ((g + 7) // 8) for g in groups]
+    nq = sum(qw * qh for qw, qh in qdims)
+    off_x = _r256(4 * nq)
+    off_o = off_x + _r256(sum(nslots) // 4)
+    assert raw.size == off_o + _r256(4 * sum(nslots))
+    cost = raw[:4 * nq].view(np.float32)
+    xmap = raw[off_x:off_x + sum(nslots) // 4].view(np.int8)
+    order = raw[off_o:off_o + 4 * sum(nslots)].view(np.int32)
+    qb = sb = 0
+    for (qw, qh), ng, ns in zip(qdims, groups, nslots):
+        c = cost[qb:qb + qw * qh]
+        xm = xmap[sb // 4:sb // 4 + ng].astype(np.int64)
+        sl = order[sb:sb + ns]
+        assert np.all(c >= 0.0) and np.all((xm >= 0) & (xm < 8))
+        blocks = sl[sl >= 0]
+        assert np.array_equal(np.sort(blocks), np.arange(qw * qh)) and np.all(sl >= -1)
+        gpx = np.bincount(xm, minlength=8)
+        assert gpx.max() - gpx.min() <= 1, gpx
+        mx = np.float32(c.max())
+        scale = np.float32(63.0) / mx if mx > 0 else np.float32(0.0)
+        level = 63 - np.clip((c * scale).astype(np.int32), 0, 63)
+        for x in range(8):
+            col = sl[x::8]
+            k = int(np.sum(col >= 0))
+            assert np.all(col[:k] >= 0) and np.all(col[k:] == -1), x
+            b = col[:k]
+            g = (b // qw // 2) * ((qw + 1) // 2) + (b % qw) // 2
+            assert np.all(xm[g] == x), x
+            assert np.all(np.diff(level[b]) >= 0), x
+        qb += qw * qh
+        sb += ns
+    say("%s: %d views, %d blocks in %d slots" % (name, len(views), nq, sum(nslots)))
+
+
 def test_workspace_errors():
     import paper_1707_01170_amd as P
     from paper_1707_01170_amd import _lib as L
