@@ -102,17 +102,16 @@ class Server:
         self.max_views = max_views
         self.max_px = max_pixels_per_launch
         # schedule: launches deal their blocks longest first (lr_render_scheduled), in a
-        # workspace per stream (one launch in flight per stream) for the largest launch:
-        # max_views views of max_pixels_per_launch pixels in all, in blocks of 16x16
+        # workspace per stream (one launch in flight per stream), sized up front for
+        # max_views square views of max_pixels_per_launch pixels in all and grown when a
+        # launch needs more (lr_render_workspace_size of its views)
         self.workspaces = None
         if schedule:
-            blocks = max_pixels_per_launch // 256 + max_views * (2 * ((max_pixels_per_launch ** 0.5) // 16 + 2) + 1)
-            nbytes = 2 * (int(blocks) * 4 + 255) // 256 * 256
-            self.workspaces = []
-            for _ in range(n_streams):
-                ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
-                off = (-ws.data_ptr()) % 256
-                self.workspaces.append(ws[off:off + nbytes])
+            from .api import view_array
+            side = max(16, int((max_pixels_per_launch // max_views) ** 0.5))
+            probe = [_square_view(side) for _ in range(max_views)]
+            self.workspaces = [_workspace(_workspace_bytes(view_array(probe)[0], max_views), dev)
+                               for _ in range(n_streams)]
 
     def run(self, requests: Sequence, keep_images: bool = False, time_scale: float = 1.0) -> ServeStats:
         """Serve requests (objects with .arrival_s and .view) in real time.
@@ -168,6 +167,9 @@ class Server:
                         L.check(L.lib().lr_render(_byref(s), arr, len(views), _ptr(self.arena.buf), None,
                                                   _stream_handle(self.streams[si])))
                     else:
+                        need = _workspace_bytes(arr, len(views))
+                        if self.workspaces[si].numel() < need:   # the stream has no launch in flight
+                            self.workspaces[si] = _workspace(need, dev)
                         ws = self.workspaces[si]
                         L.check(L.lib().lr_render_scheduled(_byref(s), arr, len(views), _ptr(self.arena.buf), None,
                                                             _ptr(ws), ws.numel(), _stream_handle(self.streams[si])))
@@ -233,6 +235,27 @@ def _view_array_at(views, offsets):
     from .api import view_array
     arr, _ = view_array(views, offsets)
     return arr
+
+
+def _workspace_bytes(arr, n: int) -> int:
+    import ctypes
+    nb = ctypes.c_int64(0)
+    L.check(L.lib().lr_render_workspace_size(arr, n, ctypes.byref(nb)))
+    return nb.value
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    """nbytes of device memory, 256-byte aligned."""
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + nbytes]
+
+
+def _square_view(side: int):
+    """A side x side orthographic view along z (only its size matters here)."""
+    from types import SimpleNamespace
+    return SimpleNamespace(proj="ortho", width=side, height=side, eye=(0.5, 0.5, -1.0), fwd=(0.0, 0.0, 1.0),
+                           right=(1.0, 0.0, 0.0), up=(0.0, 1.0, 0.0), tx=0.5, ty=0.5)
 
 
 def _byref(s):

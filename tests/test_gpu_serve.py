@@ -53,6 +53,26 @@ def test_results_identical_alone_and_in_the_mix(dtype, time_scale, schedule):
         % (dtype, st.p50_ms, st.p99_ms, st.launches, st.mean_views_per_launch, st.max_inflight))
 
 
+def test_scheduled_workspace_grows():
+    """Cost-ordered serving sized up front for small launches: thin and large
+    requests need more dealing-order workspace than that, the stream's
+    workspace grows before such a launch, and every image is still the same
+    bits as the request rendered alone."""
+    from paper_1707_01170_amd.serve import Server, render_alone
+    say("[gpu] serve, scheduled workspace growth")
+    _, sc = scene("blobs50k", dtype="f16")
+    rng = np.random.default_rng(4)
+    dirs = lrgen.random_directions(rng, 24)
+    shapes = [(1, 900), (700, 3), (16, 16), (300, 260), (5, 517), (64, 1000)]
+    reqs = [Req(0.0, lrgen.sphere_view(dirs[k], *shapes[k % len(shapes)])) for k in range(24)]
+    srv = Server(sc, budget_bytes=16 * 900 * 600, n_streams=2, max_pixels_per_launch=64 * 64, schedule=True)
+    small = min(w.numel() for w in srv.workspaces)
+    st = srv.run(reqs, keep_images=True, time_scale=0.0)
+    assert st.n == 24 and max(w.numel() for w in srv.workspaces) > small
+    for r in st.results:
+        assert torch.equal(r.image, render_alone(sc, reqs[r.index].view)), r.index
+
+
 def test_tight_budget_queues_instead_of_failing():
     from paper_1707_01170_amd.serve import Server
     _, sc = scene("scalar20k")
