@@ -85,30 +85,36 @@ def flops_per_sample(p: int, ncomp: int) -> int:
 ADJOINT_EXTRA_FLOPS = {1: 40 + 30 + 24, 2: 40 + 30 + 72, 3: 40 + 30 + 160}
 
 
-def cpu_baseline(wl, n_rays: int, seed: int = 11):
-    """The FP64 oracle (schedule-matched mode) on n_rays seeded pixels of the
-    view, split over a fork pool of the host cores.  Returns samples/s, the
-    cores used, the samples, the wall time, and the pixels with their oracle
-    RGBA (compared with the GPU frames afterwards)."""
+def oracle_pixels(wl, view, ii, jj):
+    """The FP64 oracle's RGBA (schedule-matched mode) of pixels (ii, jj) of a
+    view, over a fork pool of the host cores.  Returns (samples, seconds,
+    cores, rgba).  Runs before any GPU initialisation (the pool forks)."""
     import multiprocessing as mp
 
     from oracle.bspline import LREvaluator
     from oracle.lookup import ElementIndex
-    view = wl.views[0]
-    rng = np.random.default_rng(seed)
-    ii = rng.integers(0, view.width, n_rays)
-    jj = rng.integers(0, view.height, n_rays)
     ev, ei = LREvaluator(wl.spline), ElementIndex(wl.spline.elem_box)
     cores = min(len(os.sched_getaffinity(0)), 16)
-    chunks = np.array_split(np.arange(n_rays), cores)
+    chunks = np.array_split(np.arange(len(ii)), cores)
     global _CPU_JOB
     _CPU_JOB = (wl, view, ev, ei, ii, jj)
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(cores) as pool:
         parts = pool.map(_cpu_chunk, chunks)
     dt = time.perf_counter() - t0
-    counts = sum(c for c, _ in parts)
-    rgba = np.concatenate([r for _, r in parts])
+    return sum(c for c, _ in parts), dt, cores, np.concatenate([r for _, r in parts])
+
+
+def cpu_baseline(wl, n_rays: int, seed: int = 11):
+    """The FP64 oracle (schedule-matched mode) on n_rays seeded pixels of the
+    view, split over a fork pool of the host cores.  Returns samples/s, the
+    cores used, the samples, the wall time, and the pixels with their oracle
+    RGBA (compared with the GPU frames afterwards)."""
+    view = wl.views[0]
+    rng = np.random.default_rng(seed)
+    ii = rng.integers(0, view.width, n_rays)
+    jj = rng.integers(0, view.height, n_rays)
+    counts, dt, cores, rgba = oracle_pixels(wl, view, ii, jj)
     return float(counts) / dt, cores, int(counts), dt, (ii, jj, rgba)
 
 
@@ -134,6 +140,95 @@ def accuracy(frame, view, oracle_pix):
 def torch_index(a):
     import torch
     return torch.from_numpy(np.asarray(a, dtype=np.int64))
+
+
+# The other workloads, each as its parity tests and legs run it: name, label,
+# forest blocks per axis, Bezier block storage, and the view (None: the
+# workload's own views; "serve2048": the first 2048^2 request of the serving
+# stream).  Rays against the oracle: every pixel of a view up to 64^2, else
+# 1 024 seeded pixels of the first view.
+PER_CONFIG = (("scalar_ortho64", "scalar (2,2,2), 4^3 mesh + 20 refinements, 64x64 ortho along z, 256 fixed steps",
+               16, "f32", None),
+              ("blobs50k", "scalar (3,3,3), ~50k elements, 1024x1024 persp, Eq. 4 steps", 256, "f32", None),
+              ("blobs50k", "serving's largest request: the blob volume at 2048x2048, FP16 blocks, forest 128^3",
+               128, "f16", "serve2048"),
+              ("scalar20k", "scalar (2,2,2), ~20k elements, 4 x 512x512 persp, Eq. 4 steps (the differentiable "
+               "step's forward)", 128, "f32", None))
+
+
+def per_config_views(name, which):
+    import lrgen
+    wl = lrgen.cached(name)
+    if which == "serve2048":
+        return wl, [next(r.view for r in lrgen.blob_requests() if r.view.width == 2048)]
+    return wl, list(wl.views)
+
+
+def per_config_oracle(seed: int = 13):
+    """Oracle pixels of every PER_CONFIG workload (before GPU initialisation)."""
+    out = []
+    for name, _, _, _, which in PER_CONFIG:
+        wl, views = per_config_views(name, which)
+        v = views[0]
+        if v.width * v.height <= 64 * 64:
+            jj, ii = np.divmod(np.arange(v.width * v.height), v.width)
+        else:
+            rng = np.random.default_rng(seed)
+            ii, jj = rng.integers(0, v.width, 1024), rng.integers(0, v.height, 1024)
+        _, dt, _, rgba = oracle_pixels(wl, v, ii, jj)
+        log("oracle pixels of %s (%s): %d rays in %.1f s" % (name, which or "own views", len(ii), dt))
+        out.append((ii, jj, rgba))
+    return out
+
+
+def per_config(dev, oracle, steps: int = 20):
+    """Each other workload: frame time (p50/p99 over launches timed with HIP
+    events), samples/s and frames/s, the fraction of the FP32 vector peak at
+    the algorithmic flops per sample, the frame's pixels against the oracle,
+    and the element look-up against the oracle's on 65 536 points (uniform,
+    plus corners of elements: dyadic points on faces) -- bit-exact or not."""
+    import torch
+
+    import paper_1707_01170_amd as P
+    from oracle.lookup import ElementIndex
+    res = []
+    for (name, label, blocks, dtype, which), opix in zip(PER_CONFIG, oracle):
+        wl, views = per_config_views(name, which)
+        vol = P.Volume(wl.spline, blocks=blocks, dtype=dtype, device=dev)
+        sc = P.Scene(vol, P.RenderParams.of(wl))
+        out, _, ns = P.render(sc, views, nsamples=True)
+        samples = int(ns.to(torch.int64).sum())
+        ws = P.render_workspace(views, dev)
+        stream = torch.cuda.current_stream(dev)
+        for _ in range(3):
+            P.render(sc, views, out=out, workspace=ws)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for a, b in ev:
+            a.record(stream)
+            P.render(sc, views, out=out, workspace=ws)
+            b.record(stream)
+        torch.cuda.synchronize()
+        t = np.array([a.elapsed_time(b) for a, b in ev])
+        acc = accuracy(out[:views[0].width * views[0].height], views[0], opix)
+        rng = np.random.default_rng(17)
+        box = wl.spline.elem_box
+        pts = np.concatenate([rng.random((65536 - 4096, 3)), box[rng.integers(0, box.shape[0], 4096), :3]])
+        ids = P.lookup(vol, pts.astype(np.float32)).cpu().numpy()
+        ref = ElementIndex(box).find(pts.astype(np.float32).astype(np.float64))
+        fl = flops_per_sample(vol.p[0], vol.ncomp) * samples / (t.mean() / 1e3) / 1e12
+        r = {"workload": label, "views": [[v.width, v.height] for v in views], "blocks": dtype,
+             "forest_blocks": blocks, "samples_per_frame": samples, "ms_mean": float(t.mean()),
+             "p50_ms": float(np.percentile(t, 50)), "p99_ms": float(np.percentile(t, 99)),
+             "samples_per_s": samples / (t.mean() / 1e3), "frames_per_s": 1e3 / t.mean(),
+             "roofline_frac": fl / PEAK_FP32_TFLOPS, "accuracy": dict(acc, rays=int(len(opix[0]))),
+             "lookup_bit_exact": bool(np.array_equal(ids, ref)), "lookup_points": int(len(pts))}
+        log("%s: %.3f ms (p99 %.3f), %.3g samples/s, %.1f%% of the FP32 peak; vs oracle max %.2e rms %.2e "
+            "on %d rays; look-up bit-exact %s" % (name if which is None else which, r["ms_mean"], r["p99_ms"],
+                                                  r["samples_per_s"], 100 * r["roofline_frac"], acc["max"],
+                                                  acc["rms"], len(opix[0]), r["lookup_bit_exact"]))
+        res.append(r)
+        del vol, sc, out, ws
+    return res
 
 
 def adjoint_step(dev, steps: int = 10):
@@ -443,6 +538,8 @@ def main():
                     help="also time every look-up structure (forest sizes, octree) on the 1080p and blob workloads")
     ap.add_argument("--dispatch-study", action="store_true",
                     help="also time hardware dispatch against persistent work queues on the 1080p and blob workloads")
+    ap.add_argument("--no-configs", dest="configs", action="store_false",
+                    help="skip the other workloads (time, accuracy against the oracle, look-up check)")
     ap.add_argument("--serve", type=int, default=1000,
                     help="requests of the serving stream on the blob volume with FP16 blocks (0: skip)")
     args = ap.parse_args()
@@ -468,6 +565,7 @@ def main():
                "sample": "%d seeded rays of the 1920x1080 view (%d samples, %.1f s), FP64, schedule-matched"
                          % (args.cpu_rays, nsmp, dt)}
         log("oracle %.3e samples/s on %d cores" % (sps, cores))
+    cfg_oracle = per_config_oracle() if args.configs else None
 
     import torch
 
@@ -565,6 +663,7 @@ def main():
     sweep = [lookup_sweep(dev, n) for n in ("vortex200k", "blobs50k")] if args.lookup_sweep else None
     study = ([dispatch_study(dev, "vortex200k", blocks=256), dispatch_study(dev, "blobs50k", blocks=128)]
              if args.dispatch_study else None)
+    configs = per_config(dev, cfg_oracle) if cfg_oracle is not None else None
     serving = None
     if args.serve > 0:
         serving = serve_stream(args.serve, dev)
@@ -609,6 +708,7 @@ def main():
         "illumination": illumination,
         "fp16_storage": fp16,
         "streamlines": lines,
+        "per_config": configs,
     }
     if sweep is not None:
         res["lookup_sweep"] = sweep
