@@ -9,7 +9,9 @@ counted by a counting launch before the timed region.
 
 Prints one JSON line: spline samples/s (value), frames/s, p50/p99 frame
 latency, the roofline object of the render kernel, and the FP64 oracle timed
-on a bounded sample of the same workload on the host cores.
+on a bounded sample of the same workload on the host cores; alongside, the
+timed frame's accuracy against the oracle, the FP16-storage, illuminated,
+streamline, adjoint and serving legs, and the other workloads (per_config).
 """
 from __future__ import annotations
 
