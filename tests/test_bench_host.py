@@ -90,3 +90,19 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120, cwd=ROOT)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_per_config_workloads():
+    """The other workloads of the bench line: each names a cached workload
+    with views, the serving entry picks the stream's first 2048^2 request,
+    and the forest and storage are ones the library builds."""
+    for name, label, blocks, dtype, which in bench.PER_CONFIG:
+        wl, views = bench.per_config_views(name, which)
+        assert views and label and dtype in ("f32", "f16")
+        assert blocks in (16, 64, 128, 256)
+        if which == "serve2048":
+            assert (views[0].width, views[0].height) == (2048, 2048)
+        else:
+            assert views == list(wl.views)
+    names = [c[0] for c in bench.PER_CONFIG]
+    assert names == ["scalar_ortho64", "blobs50k", "blobs50k", "scalar20k"]
