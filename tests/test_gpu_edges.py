@@ -1,5 +1,5 @@
 """GPU edge cases against the oracle: camera inside the volume, views that miss,
-one-pixel and ragged views, degrees 1 and 3, a single-element volume, the
+one-pixel and ragged views, degrees 1 and 3 (scalar and 3-component), a single-element volume, the
 sample cap, early termination, FP16 blocks in the schedule."""
 import copy
 
@@ -87,6 +87,38 @@ def test_degrees_one_and_three(p, mode):
     for k in range(4):
         c = int(cnt[k])
         assert np.array_equal(t[k, :c], sched[k][0][:c]) and np.array_equal(e[k, :c], sched[k][1][:c])
+
+
+@pytest.mark.parametrize("p,mode,dtype", [(1, "adaptive", "f32"), (3, "adaptive", "f32"), (1, "fixed", "f32"),
+                                          (3, "fixed", "f32"), (1, "adaptive", "f16"), (3, "adaptive", "f16")])
+def test_vector_degrees_one_and_three(p, mode, dtype):
+    """3-component fields of degrees 1 and 3 (the hue colouring: |v| through
+    the table, hue from the direction; value range [0, max |c_i|]) against
+    the oracle with FP32 and FP16 blocks; the schedule bit for bit on a few
+    rays."""
+    import paper_1707_01170_amd as P
+    from oracle import render as orr
+    from oracle.bspline import LREvaluator
+    from gpu_util import TOL_F16
+    s = lrgen.small_random(p=(p, p, p), n=(4, 4, 4), n_ref=40, seed=52 + p, ncomp=3)
+    s = s.with_coef(2.0 * s.coef - 1.0)          # components of both signs: the hue covers its circle
+    vmax = float(np.sqrt((s.coef ** 2).sum(axis=1)).max())
+    views = [lrgen.sphere_view([0.5, 0.7, -0.4], 40, 30)]
+    wl = _wl(s, views, step_mode=mode, n_fixed=97, vmax=vmax, color="hue")
+    sc, rgba, ns, ref, rns = _both(wl, blocks=8, dtype=dtype)
+    err, rms = peak_rel(rgba, ref)
+    say("vector degree %d %s %s: peak-rel %.3e rms %.3e" % (p, mode, dtype, err, rms))
+    assert err <= (TOL_F32 if dtype == "f32" else TOL_F16)
+    assert np.array_equal(ns > 0, rns > 0)
+    hit = np.nonzero(rns > 0)[0]                 # four pixels whose rays meet the volume
+    pick = hit[np.linspace(0, hit.size - 1, 4).astype(int)]
+    ii, jj = pick % views[0].width, pick // views[0].width
+    t, e, ds, cnt = (x.cpu().numpy() for x in P.trace(sc, views[0], np.stack([ii, jj], 1), max_out=4096))
+    _, n_o, recs = orr.render_view(wl, views[0], orr.LRField(LREvaluator(s)), ii=ii, jj=jj, record=True)
+    sched = per_ray_schedule(recs, 4)
+    for k in range(4):
+        c = int(cnt[k])
+        assert c > 0 and np.array_equal(t[k, :c], sched[k][0][:c]) and np.array_equal(e[k, :c], sched[k][1][:c])
 
 
 def test_single_element_volume():
