@@ -60,6 +60,47 @@ def test_shaded_images_match_oracle(name, w, h, shading):
     assert err <= TOL_F32
 
 
+@pytest.mark.parametrize("p,ncomp,shading", [(1, 1, "headlight"), (1, 3, "directional"), (3, 3, "headlight")])
+def test_shaded_other_degrees_match_oracle(p, ncomp, shading):
+    """Illumination of the degrees and component counts the named volumes do
+    not cover (degree 1 scalar and vector, degree 3 vector; components of both
+    signs), against the oracle's LR-spline derivatives."""
+    import lrgen
+    import paper_1707_01170_amd as P
+    from oracle import render as orr
+    from oracle.bspline import LREvaluator
+    from oracle.lookup import ElementIndex
+    say("[gpu] shading degree %d, %d components, %s" % (p, ncomp, shading))
+    s = lrgen.small_random(p=(p, p, p), n=(4, 4, 4), n_ref=40, seed=71 + p + ncomp, ncomp=ncomp)
+    if ncomp == 3:
+        s = s.with_coef(2.0 * s.coef - 1.0)
+        vmin, vmax, color = 0.0, float(np.sqrt((s.coef ** 2).sum(axis=1)).max()), "hue"
+    else:
+        vmin, vmax, color = 0.0, 1.0, "lut"
+    view = lrgen.sphere_view([-0.6, 0.5, 0.6], 44, 32)
+    wl = lrgen.Workload("shade", s, lrgen.default_lut(), vmin, vmax, "adaptive", 64, color, [view])
+    light = (0.48, -0.6, 0.64)
+    vol = P.Volume(s, blocks=8)
+    out = {}
+    for sh in ("none", shading):
+        prm = dataclasses.replace(P.RenderParams.of(wl), shading=sh, light=light)
+        rgba, _, ns = P.render(P.Scene(vol, prm), [view], nsamples=True)
+        torch.cuda.synchronize()
+        out[sh] = (rgba.cpu().numpy(), ns.cpu().numpy())
+    jj, ii = np.meshgrid(np.arange(view.height), np.arange(view.width), indexing="ij")
+    ref, rns, _ = orr.render_view(wl, view, orr.LRField(LREvaluator(s)), eidx=ElementIndex(s.elem_box),
+                                  ii=ii.ravel(), jj=jj.ravel(), shading=shading, light=light)
+    got, ns = out[shading]
+    err, rms = peak_rel(got, ref)
+    plain = out["none"][0]
+    changed = np.abs(plain[:, :3] - got[:, :3]).max() / max(np.abs(plain).max(), 1e-9)
+    say("shaded degree %d x%d %s: peak-rel %.3e rms %.3e (shading changed the image by %.3f)"
+        % (p, ncomp, shading, err, rms, changed))
+    assert np.array_equal(ns > 0, rns > 0)
+    assert changed > 0.05
+    assert err <= TOL_F32
+
+
 def test_linear_field_constant_intensity():
     """A linear field has one normal: the shaded image is I times the plain one
     in colour and identical in opacity (directional light)."""
