@@ -147,7 +147,7 @@ def torch_index(a):
 # The other workloads, each as its parity tests and legs run it: name, label,
 # forest blocks per axis, Bezier block storage, and the view (None: the
 # workload's own views; "serve2048": the first 2048^2 request of the serving
-# stream).  Rays against the oracle: every pixel of a view up to 64^2, else
+# stream, launched as the server launches it, in centre-out order).  Rays against the oracle: every pixel of a view up to 64^2, else
 # 1 024 seeded pixels of the first view.
 PER_CONFIG = (("scalar_ortho64", "scalar (2,2,2), 4^3 mesh + 20 refinements, 64x64 ortho along z, 256 fixed steps",
                16, "f32", None),
@@ -202,12 +202,13 @@ def per_config(dev, oracle, steps: int = 20):
         samples = int(ns.to(torch.int64).sum())
         ws = P.render_workspace(views, dev)
         stream = torch.cuda.current_stream(dev)
+        order = which != "serve2048"            # the server launches lr_render (centre-out)
         for _ in range(3):
-            P.render(sc, views, out=out, workspace=ws)
+            P.render(sc, views, out=out, workspace=ws, schedule=order)
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         for a, b in ev:
             a.record(stream)
-            P.render(sc, views, out=out, workspace=ws)
+            P.render(sc, views, out=out, workspace=ws, schedule=order)
             b.record(stream)
         torch.cuda.synchronize()
         t = np.array([a.elapsed_time(b) for a, b in ev])
