@@ -60,17 +60,21 @@ def test_shaded_images_match_oracle(name, w, h, shading):
     assert err <= TOL_F32
 
 
-@pytest.mark.parametrize("p,ncomp,shading", [(1, 1, "headlight"), (1, 3, "directional"), (3, 3, "headlight")])
-def test_shaded_other_degrees_match_oracle(p, ncomp, shading):
+@pytest.mark.parametrize("p,ncomp,shading,dtype", [(1, 1, "headlight", "f32"), (1, 3, "directional", "f32"),
+                                                  (3, 3, "headlight", "f32"), (3, 3, "headlight", "f16"),
+                                                  (1, 3, "directional", "f16")])
+def test_shaded_other_degrees_match_oracle(p, ncomp, shading, dtype):
     """Illumination of the degrees and component counts the named volumes do
     not cover (degree 1 scalar and vector, degree 3 vector; components of both
-    signs), against the oracle's LR-spline derivatives."""
+    signs), against the oracle's LR-spline derivatives; FP16 blocks against
+    the FP16 bound."""
     import lrgen
     import paper_1707_01170_amd as P
     from oracle import render as orr
     from oracle.bspline import LREvaluator
     from oracle.lookup import ElementIndex
-    say("[gpu] shading degree %d, %d components, %s" % (p, ncomp, shading))
+    from gpu_util import TOL_F16
+    say("[gpu] shading degree %d, %d components, %s, %s" % (p, ncomp, shading, dtype))
     s = lrgen.small_random(p=(p, p, p), n=(4, 4, 4), n_ref=40, seed=71 + p + ncomp, ncomp=ncomp)
     if ncomp == 3:
         s = s.with_coef(2.0 * s.coef - 1.0)
@@ -80,7 +84,7 @@ def test_shaded_other_degrees_match_oracle(p, ncomp, shading):
     view = lrgen.sphere_view([-0.6, 0.5, 0.6], 44, 32)
     wl = lrgen.Workload("shade", s, lrgen.default_lut(), vmin, vmax, "adaptive", 64, color, [view])
     light = (0.48, -0.6, 0.64)
-    vol = P.Volume(s, blocks=8)
+    vol = P.Volume(s, blocks=8, dtype=dtype)
     out = {}
     for sh in ("none", shading):
         prm = dataclasses.replace(P.RenderParams.of(wl), shading=sh, light=light)
@@ -94,11 +98,11 @@ def test_shaded_other_degrees_match_oracle(p, ncomp, shading):
     err, rms = peak_rel(got, ref)
     plain = out["none"][0]
     changed = np.abs(plain[:, :3] - got[:, :3]).max() / max(np.abs(plain).max(), 1e-9)
-    say("shaded degree %d x%d %s: peak-rel %.3e rms %.3e (shading changed the image by %.3f)"
-        % (p, ncomp, shading, err, rms, changed))
+    say("shaded degree %d x%d %s %s: peak-rel %.3e rms %.3e (shading changed the image by %.3f)"
+        % (p, ncomp, shading, dtype, err, rms, changed))
     assert np.array_equal(ns > 0, rns > 0)
     assert changed > 0.05
-    assert err <= TOL_F32
+    assert err <= (TOL_F32 if dtype == "f32" else TOL_F16)
 
 
 def test_linear_field_constant_intensity():
